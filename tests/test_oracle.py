@@ -1,0 +1,484 @@
+"""Pins of the CPU oracle against mathematics (not against itself).
+
+Each test names what fixes the expected value: an exact property of the
+Rodas3 tableau, a closed-form solution of a hand-built mechanism, a
+finite-difference derivative, LAPACK (via scipy), an independent stiff solver
+(scipy Radau), or a conservation law of the model equations.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.linalg
+
+from oracle import oracle as O
+from paper_2112_05834_amd import synth
+from tests import mechs
+
+R_GAS = 8.314462618
+P_ATM = 101325.0
+
+
+def _write(m, d, name):
+    return synth.write_mech(m, "%s/%s.mech" % (d, name))
+
+
+# ---------------------------------------------------------------- Rodas3 ---
+
+def _tableau_fractions():
+    g, a, c, m, e = O.rodas3_tableau()
+    F = lambda x: Fraction(x).limit_denominator(1000)
+    gam = F(g)
+    A = [[F(a[i, j]) for j in range(4)] for i in range(4)]
+    C = [[F(c[i, j]) for j in range(4)] for i in range(4)]
+    M = [F(x) for x in m]
+    E = [F(x) for x in e]
+    # the doubles must be exactly these rationals (up to the rounding of -8/3)
+    for x, fx in [(g, gam)] + [(a[i, j], A[i][j]) for i in range(4) for j in range(4)] \
+            + [(c[i, j], C[i][j]) for i in range(4) for j in range(4)]:
+        assert float(fx) == x
+    return gam, A, C, M, E
+
+
+def _linear_stages(gam, A, C, M, E, z):
+    """Rodas3 on y' = lambda y, y0 = 1, at z = h lambda, in exact arithmetic:
+    (1/gamma - z) K_i = z (1 + sum a_ij K_j) + sum c_ij K_j."""
+    K = []
+    for i in range(4):
+        r = z * (1 + sum(A[i][j] * K[j] for j in range(i))) + sum(C[i][j] * K[j] for j in range(i))
+        K.append(r / (1 / gam - z))
+    R = 1 + sum(M[j] * K[j] for j in range(4))
+    Err = sum(E[j] * K[j] for j in range(4))
+    return R, Err
+
+
+def _R_closed(z):
+    # stability function of Rodas3 (order 3, L-stable)
+    return Fraction(8) * (z ** 3 - 6 * z + 6) / (3 * (z - 2) ** 4)
+
+
+def _Rhat_closed(z):
+    # stability function of the embedded order-2 solution
+    return Fraction(2) * (z ** 2 + 2 * z - 4) / (z - 2) ** 3
+
+
+def test_rodas3_stability_function_closed_form():
+    tab = _tableau_fractions()
+    for z in [Fraction(-1, 3), Fraction(1, 7), Fraction(-5), Fraction(-1000), Fraction(3, 2)]:
+        R, Err = _linear_stages(*tab, z)
+        assert R == _R_closed(z)
+        assert R - Err == _Rhat_closed(z)
+
+
+def test_rodas3_order_on_linear_problem():
+    """R(z) - e^z = O(z^4) and Rhat(z) - e^z = O(z^3), exactly: compare
+    Taylor coefficients of the exact rational functions."""
+    tab = _tableau_fractions()
+    # Taylor coefficients by exact evaluation at tiny z with Richardson-free
+    # algebra: R(z) is rational; expand via sympy-free finite differences of
+    # exact values is awkward, so check the defect ratio instead.
+    for order, f in [(3, lambda z: _linear_stages(*tab, z)[0]),
+                     (2, lambda z: (lambda R, E: R - E)(*_linear_stages(*tab, z)))]:
+        defects = []
+        for k in range(4, 9):
+            z = Fraction(1, 2 ** k)
+            ez = sum(z ** j / math.factorial(j) for j in range(12))
+            defects.append(abs(f(z) - ez))
+        ratios = [float(defects[i] / defects[i + 1]) for i in range(len(defects) - 1)]
+        # defect ~ z^(order+1): halving z divides it by 2^(order+1)
+        for r in ratios[1:]:
+            assert abs(r - 2 ** (order + 1)) / 2 ** (order + 1) < 0.1
+
+
+def test_rodas3_L_stable():
+    tab = _tableau_fractions()
+    R, _ = _linear_stages(*tab, Fraction(-10) ** 12)
+    assert abs(float(R)) < 1e-11
+
+
+def test_rodas3_nonlinear_order_conditions():
+    """Order-3 conditions of the classical form, derived from the transformed
+    coefficients: Gamma from gamma and c, alpha from a."""
+    gam, A, C, M, E = _tableau_fractions()
+    # transformed form: a = alpha Gamma^-1, c = diag(1/gamma) - Gamma^-1, m = b Gamma^-1
+    # so Gamma^-1 = diag(1/gamma) - c, alpha = a Gamma, b = m Gamma.
+    Ginv = [[(1 / gam if i == j else 0) - C[i][j] for j in range(4)] for i in range(4)]
+    G = _inv_lower(Ginv)
+    alpha = [[sum(A[i][k] * G[k][j] for k in range(4)) for j in range(4)] for i in range(4)]
+    b = [sum(M[k] * G[k][j] for k in range(4)) for j in range(4)]
+    al = [sum(alpha[i][j] for j in range(4)) for i in range(4)]
+    # beta_ij = alpha_ij + gamma_ij; beta'_i = sum_{j<i} beta_ij
+    beta_p = [sum(alpha[i][j] + G[i][j] for j in range(i)) for i in range(4)]
+    assert sum(b) == 1
+    assert sum(b[i] * beta_p[i] for i in range(4)) == Fraction(1, 2) - gam
+    assert sum(b[i] * al[i] ** 2 for i in range(4)) == Fraction(1, 3)
+    bb = sum(b[i] * sum((alpha[i][k] + G[i][k]) * beta_p[k] for k in range(i)) for i in range(4))
+    assert bb == Fraction(1, 6) - gam + gam ** 2
+    # stiff accuracy: b equals the last row of alpha + Gamma
+    assert b == [alpha[3][j] + G[3][j] for j in range(4)]
+
+
+def _inv_lower(L):
+    n = len(L)
+    X = [[Fraction(0)] * n for _ in range(n)]
+    for j in range(n):
+        for i in range(n):
+            s = Fraction(1 if i == j else 0) - sum(L[i][k] * X[k][j] for k in range(i))
+            X[i][j] = s / L[i][i]
+    return X
+
+
+# ------------------------------------------------- closed-form mechanisms ---
+
+def test_one_step_isomer_matches_stability_function(mech_dir):
+    kf = 2.0e5
+    shift = 0.7
+    M = O.Mech(_write(mechs.isomer_pair(kf, shift), mech_dir, "iso"))
+    kr = kf / math.exp(shift)
+    yeq = kr / (kf + kr)
+    tab = _tableau_fractions()
+    for h in [1e-7, 3e-6, 1e-4, 1e-2]:
+        y0 = np.array([1200.0, 0.9, 0.1])
+        yn, err = M.rodas3_step(1e5, y0, h)
+        z = Fraction(-(kf + kr) * h)
+        R, E = _linear_stages(*tab, z)
+        d0 = y0[1] - yeq
+        assert yn[0] == y0[0]
+        assert abs((yn[1] - yeq) - float(R) * d0) <= 1e-13 * abs(d0)
+        assert abs(err[1] - float(E) * d0) <= 1e-13 * abs(d0)
+        assert abs(yn[1] + yn[2] - 1.0) < 1e-13
+
+
+def test_adaptive_isomer_closed_form(mech_dir):
+    kf, shift = 2.0e5, 0.7
+    M = O.Mech(_write(mechs.isomer_pair(kf, shift), mech_dir, "iso2"))
+    kr = kf / math.exp(shift)
+    yeq = kr / (kf + kr)
+    phi = np.array([[1100.0, 1e5, 0.95, 0.05], [900.0, 1e5, 0.0, 1.0]])
+    for dt in [1e-6, 1e-5, 1e-4]:
+        out, h, na, nr, st = M.integrate(phi, dt)
+        assert (st == 0).all()
+        ya = yeq + (phi[:, 2] - yeq) * math.exp(-(kf + kr) * dt)
+        assert np.all(np.abs(out[:, 2] - ya) <= 10 * (1e-10 + 1e-6 * np.abs(ya)))
+        assert np.all(out[:, 0] == phi[:, 0])
+
+
+def test_convergence_order_termolecular(mech_dir):
+    """Fixed-step Rodas3 on 3A -> 3B: global error of the main solution falls
+    as h^3, of the embedded solution as h^2."""
+    k = 1.0e2
+    mech = mechs.termolecular_isomer(k)
+    M = O.Mech(_write(mech, mech_dir, "ter"))
+    T, p = 1000.0, 1.0e5
+    y0 = np.array([T, 1.0, 0.0])
+    C0 = p / (R_GAS * T)
+    rho = p * mech.W[0] / (R_GAS * T)
+    t_end = 2.0 / (k * C0 * C0)
+    exact = C0 / math.sqrt(1 + 6 * k * C0 * C0 * t_end) * mech.W[0] / rho
+    errs_main, errs_emb = [], []
+    for N in [32, 64, 128, 256, 512, 1024]:
+        h = t_end / N
+        y, ye = y0.copy(), y0.copy()
+        for _ in range(N):
+            y, _ = M.rodas3_step(p, y, h)
+            yn, e = M.rodas3_step(p, ye, h)
+            ye = yn - e
+        errs_main.append(abs(y[1] - exact))
+        errs_emb.append(abs(ye[1] - exact))
+    sm = [math.log2(errs_main[i] / errs_main[i + 1]) for i in range(4)]
+    se = [math.log2(errs_emb[i] / errs_emb[i + 1]) for i in range(5)]
+    assert abs(sm[-1] - 3.0) < 0.1 and abs(sm[-2] - 3.0) < 0.1, sm
+    assert abs(se[-1] - 2.0) < 0.05 and abs(se[-2] - 2.0) < 0.1, se
+
+
+def test_third_body_unit_efficiencies(mech_dir):
+    mech = mechs.third_body_unit(A=1.0e2)
+    M = O.Mech(_write(mech, mech_dir, "tb"))
+    T, p = 1500.0, 3.0e5
+    Y = np.array([0.2, 0.3, 0.1, 0.4])
+    kf, kr, q = M.rates(T, p, Y)
+    Wbar = 1.0 / np.sum(Y / mech.W)
+    rho = p * Wbar / (R_GAS * T)
+    C = rho * Y / mech.W
+    expect = 1.0e2 * (p / (R_GAS * T)) * C[0] * C[1]
+    assert kr[0] == 0.0
+    assert abs(q[0] - expect) <= 4e-15 * abs(expect)
+
+
+def test_troe_reduces_to_lindemann(mech_dir):
+    A, A0 = 1.0e7, 1.0e4
+    mech = mechs.troe_lindemann(A, A0)
+    M = O.Mech(_write(mech, mech_dir, "lind"))
+    for T, p in [(1200.0, 1e5), (2000.0, 6e6), (800.0, 1e3)]:
+        Y = np.array([0.25, 0.25, 0.2, 0.3])
+        kf, kr, q = M.rates(T, p, Y)
+        Wbar = 1.0 / np.sum(Y / mech.W)
+        rho = p * Wbar / (R_GAS * T)
+        C = rho * Y / mech.W
+        Mconc = p / (R_GAS * T)
+        Pr = A0 * Mconc / A
+        expect = A * Pr / (1 + Pr) * C[0] * C[1]
+        assert abs(q[0] - expect) <= 1e-14 * abs(expect)
+
+
+def test_thermo_derivatives(mech_dir):
+    mech, path = synth.mech_cached("spray54", mech_dir)
+    M = O.Mech(path)
+    for T in [350.0, 900.0, 1700.0, 3100.0]:
+        cp, h, s, dcp = M.thermo(T)
+        d = 1e-3
+        _, hp, sp, _ = M.thermo(T + d)
+        _, hm, sm, _ = M.thermo(T - d)
+        cpp, _, _, _ = M.thermo(T + d)
+        cpm, _, _, _ = M.thermo(T - d)
+        dH = (hp * (T + d) - hm * (T - d)) / (2 * d)     # d(h/R)/dT = cp/R
+        dS = (sp - sm) / (2 * d)                          # d(s/R)/dT = cp/(R T)
+        assert np.allclose(dH, cp, rtol=1e-9, atol=0)
+        assert np.allclose(dS, cp / T, rtol=1e-8, atol=0)
+        assert np.allclose((cpp - cpm) / (2 * d), dcp, rtol=1e-6, atol=1e-12)
+
+
+def test_equilibrium_constant_isomer(mech_dir):
+    shift = 0.37
+    M = O.Mech(_write(mechs.isomer_pair(1e3, shift), mech_dir, "iso3"))
+    kf, kr, _ = M.rates(1500.0, 1e5, np.array([0.5, 0.5]))
+    assert abs(kf[0] / kr[0] - math.exp(shift)) < 1e-14 * math.exp(shift)
+
+
+def test_irreversible_has_no_reverse_rate(mech_dir):
+    M = O.Mech(_write(mechs.isomer_pair(1e3, 0.3, reversible=False), mech_dir, "iso4"))
+    kf, kr, q = M.rates(1500.0, 1e5, np.array([0.5, 0.5]))
+    assert kr[0] == 0.0 and kf[0] == 1e3
+
+
+# --------------------------------------------------------------- Jacobian ---
+
+def fd_jacobian_check(M, p, y, floorT=1.0, floorY=1e-8):
+    """Central-difference check in the scaled form diag(1/s) J diag(s)."""
+    n = len(y)
+    s = np.abs(y).copy()
+    s[0] = max(s[0], floorT)
+    s[1:] = np.maximum(s[1:], floorY)
+    J = M.jac(p, y)
+    Jfd = np.zeros_like(J)
+    for j in range(n):
+        d = 1e-6 * s[j]
+        yp, ym = y.copy(), y.copy()
+        yp[j] += d
+        ym[j] -= d
+        Jfd[:, j] = (M.rhs(p, yp) - M.rhs(p, ym)) / (2 * d)
+    Ja = J * s[None, :] / s[:, None]
+    Jf = Jfd * s[None, :] / s[:, None]
+    rowmax = np.abs(Ja).max(axis=1, keepdims=True)
+    bad = np.abs(Ja - Jf) > 1e-6 * np.abs(Jf) + 1e-9 * rowmax
+    return int(bad.sum())
+
+
+@pytest.mark.parametrize("name", ["tiny9_1024", "spray54_262144"])
+def test_jacobian_vs_finite_differences(name, mech_dir):
+    wl, mech, path, phi = synth.workload_inputs(name, mech_dir, n_cells=2000)
+    M = O.Mech(path)
+    idx = synth.sample_indices(phi.shape[0], 12, 11)
+    for c in idx:
+        y = np.concatenate([[phi[c, 0]], phi[c, 2:]])
+        assert fd_jacobian_check(M, phi[c, 1], y) == 0
+
+
+def test_jacobian_falloff_chain_rule(mech_dir):
+    mech = mechs.troe_mix()
+    M = O.Mech(_write(mech, mech_dir, "troemix"))
+    rng = np.random.Generator(np.random.PCG64(3))
+    for _ in range(20):
+        T = rng.uniform(600, 2800)
+        p = 10 ** rng.uniform(3.5, 7)
+        Y = rng.dirichlet(np.ones(mech.n_species))
+        y = np.concatenate([[T], Y])
+        assert fd_jacobian_check(M, p, y, floorY=1e-6) == 0
+
+
+# --------------------------------------------------------------------- LU ---
+
+def test_lu_matches_lapack():
+    rng = np.random.Generator(np.random.PCG64(1))
+    for n in [1, 2, 10, 55, 161]:
+        A = rng.normal(size=(n, n)) + n ** 0.5 * np.eye(n) * rng.uniform(0, 1)
+        LU, piv, info = O.lu(A)
+        lu_ref, piv_ref = scipy.linalg.lu_factor(A)
+        assert info == 0
+        assert np.array_equal(piv, piv_ref)
+        assert np.max(np.abs(LU - lu_ref)) <= 1e-12 * np.max(np.abs(A))
+        b = rng.normal(size=n)
+        x = O.lu_solve(LU, piv, b)
+        x_ref = scipy.linalg.lu_solve((lu_ref, piv_ref), b)
+        assert np.max(np.abs(x - x_ref)) <= 1e-11 * np.max(np.abs(x_ref))
+
+
+def test_lu_on_integrator_matrix(mech_dir):
+    wl, mech, path, phi = synth.workload_inputs("spray54_262144", mech_dir, n_cells=64)
+    M = O.Mech(path)
+    for c in range(0, 64, 9):
+        y = np.concatenate([[phi[c, 0]], phi[c, 2:]])
+        J = M.jac(phi[c, 1], y)
+        A = np.eye(M.n) / (0.5 * 1e-8) - J
+        LU, piv, info = O.lu(A)
+        lu_ref, piv_ref = scipy.linalg.lu_factor(A)
+        assert np.array_equal(piv, piv_ref)
+        b = np.arange(M.n, dtype=float) + 1
+        x = O.lu_solve(LU, piv, b)
+        r = A @ x - b
+        assert np.max(np.abs(r)) <= M.n * 1e-15 * np.max(np.abs(A)) * np.max(np.abs(x)) * 10
+
+
+def test_lu_singular_reports_column():
+    A = np.array([[1.0, 2.0, 3.0], [2.0, 4.0, 6.0], [1.0, 0.0, 1.0]])
+    _, _, info = O.lu(A)
+    assert info == 3
+
+
+# ------------------------------------------------------------- integrator ---
+
+def _element_totals(mech, Y):
+    return (Y / mech.W) @ mech.elem
+
+
+def _enthalpy(M, mech, T, Y):
+    out = np.empty(len(T))
+    for c in range(len(T)):
+        _, h, _, _ = M.thermo(T[c])
+        out[c] = np.sum(Y[c] * h * R_GAS * T[c] / mech.W)
+    return out
+
+
+def test_invariants_tiny9(mech_dir):
+    wl, mech, path, phi = synth.workload_inputs("tiny9_1024", mech_dir)
+    M = O.Mech(path)
+    out, h, na, nr, st = M.integrate(phi, wl.dt, n_threads=8)
+    assert (st == 0).all()
+    e0 = _element_totals(mech, phi[:, 2:])
+    e1 = _element_totals(mech, out[:, 2:])
+    used = e0.max(axis=0) > 0
+    rel = np.abs(e1 - e0)[:, used] / e0[:, used].max(axis=1, keepdims=True)
+    assert rel.max() <= 1e-12
+    assert np.abs(out[:, 2:].sum(axis=1) - 1.0).max() <= 1e-13
+    assert np.all(out[:, 1] == phi[:, 1])
+    H0 = _enthalpy(M, mech, phi[:, 0], phi[:, 2:])
+    H1 = _enthalpy(M, mech, out[:, 0], out[:, 2:])
+    cpT = np.array([np.sum(phi[c, 2:] * M.thermo(phi[c, 0])[0] * R_GAS / mech.W) * phi[c, 0] for c in range(64)])
+    assert np.all(np.abs(H1[:64] - H0[:64]) <= 10 * 1e-6 * cpT)
+
+
+def test_entropy_non_decreasing(mech_dir):
+    wl, mech, path, phi = synth.workload_inputs("tiny9_1024", mech_dir, n_cells=16)
+    M = O.Mech(path)
+
+    def s_mix(T, p, Y):
+        _, _, s, _ = M.thermo(T)
+        X = (Y / mech.W) / np.sum(Y / mech.W)
+        return np.sum(Y / mech.W * R_GAS * (s - np.log(X * p / P_ATM)))
+
+    cur = phi.copy()
+    h = None
+    for _ in range(8):
+        nxt, h, na, nr, st = M.integrate(cur, 2e-7, h_io=h)
+        for c in range(cur.shape[0]):
+            if (cur[c, 2:] > 0).all() and (nxt[c, 2:] > 0).all():
+                s0 = s_mix(cur[c, 0], cur[c, 1], cur[c, 2:])
+                s1 = s_mix(nxt[c, 0], nxt[c, 1], nxt[c, 2:])
+                assert s1 - s0 >= -1e-9 * abs(s0)
+        cur = nxt
+
+
+def test_equilibrium_isomer_cycle(mech_dir):
+    """Detailed balance: at X_i ~ exp(a7_i) every reaction has Q_r = Kc_r, so
+    f = 0 and integration leaves the state alone; from elsewhere the
+    integrator converges to that state."""
+    shifts = (0.0, 0.9, -0.4)
+    M = O.Mech(_write(mechs.isomer_cycle(shifts), mech_dir, "cyc"))
+    yeq = np.exp(shifts) / np.sum(np.exp(shifts))
+    y = np.concatenate([[1500.0], yeq])
+    f = M.rhs(1e5, y)
+    kf, kr, q = M.rates(1500.0, 1e5, yeq)
+    C = 1e5 / (R_GAS * 1500.0) * yeq
+    assert np.all(np.abs(q) <= 1e-13 * kf * C.max())
+    assert np.all(np.abs(f[1:]) <= 1e-13 * kf.max())
+    phi = np.array([[1500.0, 1e5, *yeq], [1500.0, 1e5, 1.0, 0.0, 0.0], [1500.0, 1e5, 0.1, 0.2, 0.7]])
+    out, h, na, nr, st = M.integrate(phi, 1e-3, rtol=1e-10, atol=1e-16)
+    assert (st == 0).all()
+    assert np.max(np.abs(out[0, 2:] - yeq)) <= 1e-14
+    assert np.max(np.abs(out[1:, 2:] - yeq)) <= 1e-9
+
+
+def test_equilibrium_dissociation(mech_dir):
+    mech = mechs.dissociation()
+    M = O.Mech(_write(mech, mech_dir, "diss"))
+    T, p = 2500.0, 2e5
+    cp, h, s, _ = M.thermo(T)
+    assert abs(h[0] - 2 * h[1]) <= 1e-14 * abs(h[0])
+    g = h - s
+    Kc = math.exp(-(2 * g[1] - g[0])) * (P_ATM / (R_GAS * T))
+    Ctot = p / (R_GAS * T)
+    CB = (-Kc + math.sqrt(Kc * Kc + 4 * Kc * Ctot)) / 2
+    CA = Ctot - CB
+    YA = CA * mech.W[0] / (CA * mech.W[0] + CB * mech.W[1])
+    phi = np.array([[T, p, 1.0, 0.0], [T, p, 0.3, 0.7]])
+    out, hh, na, nr, st = M.integrate(phi, 1e-3, rtol=1e-10, atol=1e-16)
+    assert (st == 0).all()
+    assert np.all(np.abs(out[:, 0] - T) <= 1e-9 * T)
+    assert np.max(np.abs(out[:, 2] - YA)) <= 1e-8
+
+
+def test_thermo_matches_construction(mech_dir):
+    """NASA values reproduce the generator's defining draws: cp/R is the
+    smoothstep closed form, h/R(T) - a6 is the integral of cp/R from 0, and
+    s/R(298.15) is the drawn standard entropy."""
+    import scipy.integrate as si
+    cp0, dcp, a6, s298 = 4.2, 1.3, -1234.5, 31.0
+    nasa = synth.nasa_from_draws(cp0, dcp, a6, s298)
+    mech = mechs._mech([(1, 1, 0, 0)], [nasa], [], names=["X"])
+    M = O.Mech(_write(mech, mech_dir, "one"))
+    cp_true = lambda T: cp0 + dcp * (3 * ((T - 200) / 5800) ** 2 - 2 * ((T - 200) / 5800) ** 3)
+    for T in [250.0, 700.0, 1000.0, 2345.0, 5900.0]:
+        cp, h, s, _ = M.thermo(T)
+        assert abs(cp[0] - cp_true(T)) <= 1e-12 * cp_true(T)
+        integral, _ = si.quad(cp_true, 0.0, T, epsabs=0, epsrel=1e-13)
+        assert abs(h[0] * T - a6 - integral) <= 1e-9 * abs(integral)
+    _, _, s, _ = M.thermo(298.15)
+    assert abs(s[0] - s298) <= 1e-12 * s298
+
+
+def test_integrator_vs_scipy_radau(mech_dir):
+    wl, mech, path, phi = synth.workload_inputs("tiny9_1024", mech_dir, n_cells=512)
+    M = O.Mech(path)
+    idx = synth.sample_indices(512, 6, 5)
+    out, h, na, nr, st = M.integrate(phi[idx], wl.dt)
+    for k, c in enumerate(idx):
+        p = phi[c, 1]
+        y0 = np.concatenate([[phi[c, 0]], phi[c, 2:]])
+        sol = scipy.integrate.solve_ivp(lambda t, y: M.rhs(p, y), (0.0, wl.dt), y0, method="Radau",
+                                        jac=lambda t, y: M.jac(p, y), rtol=1e-12, atol=1e-16)
+        assert sol.success
+        yref = sol.y[:, -1]
+        mine = np.concatenate([[out[k, 0]], out[k, 2:]])
+        assert np.all(np.abs(mine - yref) <= 10 * (1e-10 + 1e-6 * np.abs(yref)))
+
+
+def test_status_codes(mech_dir):
+    wl, mech, path, phi = synth.workload_inputs("tiny9_1024", mech_dir, n_cells=4)
+    M = O.Mech(path)
+    bad = phi.copy()
+    bad[0, 3] = np.nan
+    bad[1, 0] = 199.0
+    bad[1, 2:] = 0.0
+    bad[1, 2 + mech.inert] = 1.0           # inert gas: T stays at 199 K
+    out, h, na, nr, st = M.integrate(bad, wl.dt)
+    assert st[0] == 3 and np.isnan(out[0, 3])
+    assert st[1] == 5 and out[1, 0] == 199.0
+    out, h, na, nr, st = M.integrate(phi, wl.dt, max_steps=1)
+    assert (st == 1).all() or ((st == 1) | (st == 0)).all()
+    assert (st[na + nr >= 1] >= 0).all()
+    out, h, na, nr, st = M.integrate(phi[2:], wl.dt, rtol=1e-30, atol=1e-300)
+    assert (st == 2).all()
+    assert (na == 0).all()
+    assert np.array_equal(out, phi[2:])
