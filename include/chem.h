@@ -1,0 +1,213 @@
+/* chem.h -- C ABI of the MI355X stiff-chemistry integrator (libchem.so).
+ *
+ * The operation (paper: "Introduction"; "Analytical Jacobian and improved ODE
+ * solution"): each CFD cell carries a composition vector phi = (T, p, species)
+ * that is advanced over one CFD time step dt by integrating the stiff
+ * kinetics ODE f = d(phi)/dt with an implicit integrator that uses the
+ * analytical Jacobian J_ij = df_i/dphi_j and an LU factorisation with back
+ * substitution. Cells are independent; the paper balances their uneven cost
+ * across MPI ranks ("DLBFoam: Dynamic load balancing"), which this library
+ * turns into balancing across the waves of one GPU (persistent kernel with an
+ * atomic work queue, optionally ordered by a learned cost model).
+ *
+ * Model used (the paper leaves it unnamed): constant-pressure adiabatic
+ * reactor per cell with state y = (T, Y_1..Y_Ns) and p fixed; NASA-7 thermo;
+ * modified Arrhenius, third-body and Troe falloff rates; reverse rates from
+ * equilibrium constants; Rodas3 (4 stages, order 3 with embedded order 2,
+ * L-stable) with M = I/(gamma h) - J factored by LU with partial pivoting.
+ *
+ * Conventions for every int-returning call: 0 = CHEM_OK, < 0 = error code
+ * below; chem_last_error() then returns a message (thread-local, valid until
+ * the next failing call on the same thread). No call aborts the process.
+ *
+ * Device pointers: every array argument named *_dev or documented as device
+ * memory must be a device allocation on the solver's HIP device, contiguous,
+ * with the stated element type and layout. The caller owns those arrays.
+ * Calls that take a stream only enqueue work on it (no host synchronisation)
+ * unless stated; pass the hipStream_t as void* (NULL = the null stream).
+ */
+#ifndef CHEM_H
+#define CHEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define CHEM_OK 0
+#define CHEM_EINVAL (-1)       /* bad argument (null pointer, size, layout)   */
+#define CHEM_EMECH (-2)        /* mechanism file cannot be parsed / invalid   */
+#define CHEM_EHIP (-3)         /* HIP runtime error                           */
+#define CHEM_ENOMEM (-4)       /* device or host allocation failed            */
+#define CHEM_ESTATE (-5)       /* call not valid in this state               */
+#define CHEM_EUNSUPPORTED (-6) /* size not supported by the compiled kernels  */
+
+/* Per-cell status codes (status array of chem_integrate). A failed cell keeps
+ * its last accepted state in phi_out; the call itself still returns CHEM_OK. */
+#define CHEM_CELL_OK 0
+#define CHEM_CELL_MAX_STEPS 1   /* attempted steps reached opts.max_steps     */
+#define CHEM_CELL_H_UNDERFLOW 2 /* step size fell below 1e-20 s               */
+#define CHEM_CELL_NONFINITE 3   /* non-finite input (T, p or a Y)             */
+#define CHEM_CELL_SINGULAR 4    /* exact zero pivot in the LU of M            */
+#define CHEM_CELL_T_RANGE 5     /* an accepted step left T in [200, 6000] K   */
+
+/* Schedules. */
+#define CHEM_PLAIN 0              /* one launch per chemistry step, static cell-to-wave map */
+#define CHEM_PERSISTENT 1         /* resident waves pull cells from an atomic queue          */
+#define CHEM_PERSISTENT_BINNED 2  /* as 1, queue ordered by predicted cost, longest first    */
+
+typedef struct chem_mech chem_mech;     /* opaque, library owned, host side     */
+typedef struct chem_solver chem_solver; /* opaque, library owned, one HIP device */
+
+typedef struct {
+  double rtol;              /* relative tolerance (default 1e-6)                         */
+  double atol;              /* absolute tolerance, T and every Y (default 1e-10)         */
+  int32_t max_steps;        /* attempted steps per cell per chemistry step (100000)      */
+  int32_t schedule;         /* CHEM_PLAIN / CHEM_PERSISTENT / CHEM_PERSISTENT_BINNED     */
+  int32_t cells_per_wave;   /* cells integrated by one 64-lane wave; 0 = autotuned/auto  */
+  int32_t queue_chunk;      /* cells taken per atomic queue pull; 0 = auto               */
+  int32_t blocks;           /* persistent grid size in blocks; 0 = fill the device       */
+  int32_t waves_per_block;  /* 0 = auto                                                  */
+  int64_t hbm_budget_bytes; /* workspace budget for in-flight cells; 0 = 50% of free     */
+} chem_opts;
+
+/* Fill o with the defaults above. */
+void chem_opts_default(chem_opts* o);
+
+/* ---- mechanism ---------------------------------------------------------- */
+
+/* Parse the text mechanism at path (format: species with W and NASA-7
+ * coefficients, reactions with Arrhenius A [SI], b, Ea [J/mol], optional
+ * third-body efficiencies and Troe parameters). Host only. *out is owned by
+ * the caller and released with chem_mech_free. Errors: CHEM_EINVAL,
+ * CHEM_EMECH (message names the offending token). */
+int chem_mech_load(const char* path, chem_mech** out);
+int chem_mech_dims(const chem_mech* m, int32_t* n_species, int32_t* n_reactions);
+/* Algorithmic work per evaluation, counted from the mechanism's structure:
+ * flops of one right-hand side and of one analytical Jacobian (beyond the
+ * right-hand side it also yields), with each exp/log/pow counted as one
+ * transcendental (reported separately, not in the flop figures). Any output
+ * pointer may be NULL. */
+int chem_mech_work(const chem_mech* m, double* flops_rhs, double* flops_jac,
+                   double* trans_rhs, double* trans_jac);
+void chem_mech_free(chem_mech* m); /* NULL-safe */
+
+/* ---- solver ------------------------------------------------------------- */
+
+/* Bind a mechanism to HIP device hip_device: uploads the mechanism image
+ * (the part staged in LDS by every block plus thermo tables) and allocates the
+ * queue and scratch. The mechanism may be freed afterwards. Errors:
+ * CHEM_EINVAL, CHEM_EHIP, CHEM_ENOMEM, CHEM_EUNSUPPORTED (state size n = Ns+1
+ * beyond the compiled kernels). */
+int chem_solver_create(const chem_mech* m, const chem_opts* o, int32_t hip_device,
+                       chem_solver** out);
+void chem_solver_free(chem_solver* s); /* NULL-safe; synchronises the device */
+/* Replace the solver's options (same validation as create). */
+int chem_solver_set_opts(chem_solver* s, const chem_opts* o);
+int chem_solver_get_opts(const chem_solver* s, chem_opts* o);
+
+/* Integrate every cell over [0, dt] (one chemistry step).
+ *   phi_in, phi_out : device, [n_cells][2+Ns] float64 = (T [K], p [Pa], Y_1..Y_Ns);
+ *                     phi_out may alias phi_in exactly (not partially).
+ *   h_io   : device [n_cells] float64 or NULL. In: first substep (<= 0 means
+ *            dt). Out: the controller's next proposal (for chained steps).
+ *   n_acc, n_rej : device [n_cells] int32 or NULL: accepted / rejected
+ *            attempts of this call.
+ *   status : device [n_cells] int8 or NULL: CHEM_CELL_* per cell.
+ *   stream : hipStream_t; work is enqueued only.
+ * Results do not depend on the schedule, cells_per_wave, queue_chunk or
+ * blocks: every cell's arithmetic is identical (bit for bit) under all of
+ * them. n_cells = 0 is a no-op. Errors: CHEM_EINVAL (n_cells < 0, dt <= 0 or
+ * not finite, null phi, partial aliasing), CHEM_ESTATE (binned schedule
+ * without a usable model is not an error: it falls back to queue order),
+ * CHEM_EHIP. */
+int chem_integrate(chem_solver* s, int64_t n_cells, double dt, const double* phi_in,
+                   double* phi_out, double* h_io, int32_t* n_acc, int32_t* n_rej,
+                   int8_t* status, void* stream);
+
+/* n_steps chained chemistry steps of the same dt, each feeding the next (h_io
+ * carried between them), captured once into a HIP graph and replayed; phi_out
+ * holds the final state, n_acc / n_rej accumulate over the steps and status is
+ * the first non-zero status of the steps. phi_in is not modified; the library
+ * ping-pongs through an internal buffer. The graph is cached per (pointers,
+ * sizes, options) and rebuilt when they change. Errors as chem_integrate. */
+int chem_integrate_steps(chem_solver* s, int32_t n_steps, int64_t n_cells, double dt,
+                         const double* phi_in, double* phi_out, double* h_io, int32_t* n_acc,
+                         int32_t* n_rej, int8_t* status, void* stream);
+
+/* ---- kernel-level entry points (tests and roofline measurements) -------- */
+
+/* Right-hand side f(y) and analytical Jacobian at every cell's state.
+ *   phi : device [n_cells][2+Ns]; f : device [n_cells][n] (n = Ns+1, order
+ *   T, Y_1..Y_Ns); J : device [n_cells][n][n] row-major (df_i/dy_j) or NULL. */
+int chem_eval_rhs_jac(chem_solver* s, int64_t n_cells, const double* phi, double* f, double* J,
+                      void* stream);
+/* Batched LU with partial pivoting (LAPACK getrf semantics: piv[k] is the row
+ * swapped with row k at step k, 0-based; ties go to the lowest row) of
+ * row-major n x n matrices A[batch][n][n], in place; info[b] = 0 or k+1 for
+ * the first exactly-zero pivot. Then, if b is not NULL, solves A x = b for
+ * b[batch][n] in place. n must equal the solver's state size. */
+int chem_lu_batch(chem_solver* s, int64_t batch, double* A, int32_t* piv, int32_t* info,
+                  double* b, void* stream);
+
+/* ---- learned cost model (changes scheduling only, never results) ------- */
+
+/* Keep a device log of (features[4], ln substeps) per integrated cell, up to
+ * capacity records (ring; later records overwrite). capacity 0 disables. */
+int chem_log_enable(chem_solver* s, int64_t capacity);
+/* Copy the log into caller buffers (device, feats [cap][4] float32, target
+ * [cap] float32) and write the number of valid records to *n_out (host).
+ * Synchronises the stream. */
+int chem_log_fetch(chem_solver* s, float* feats_dev, float* target_dev, int64_t* n_out,
+                   void* stream);
+/* Features of every cell (device [n][4] float32), as the predictor sees them. */
+int chem_features(chem_solver* s, int64_t n_cells, double dt, const double* phi, float* feats,
+                  void* stream);
+
+typedef struct {
+  int32_t epochs;  /* passes over the samples (default 10)          */
+  int32_t batch;   /* minibatch size (default 4096)                 */
+  float lr, beta1, beta2, eps;  /* Adam (1e-3, 0.9, 0.999, 1e-8)   */
+  uint64_t seed;   /* weight init and shuffling                     */
+} chem_train_opts;
+void chem_train_opts_default(chem_train_opts* t);
+
+/* Train the 4->64->64->1 ReLU MLP (BF16 weights and activations as matmul
+ * operands, FP32 accumulation, FP32 master weights, Adam) to predict ln
+ * substeps from the 4 features, on n samples (device float32). Fits the
+ * feature standardisation and the 8 bin edges (octiles of the training
+ * predictions). Synchronises the stream. */
+int chem_model_train(chem_solver* s, int64_t n, const float* feats_dev, const float* target_dev,
+                     const chem_train_opts* t, void* stream);
+/* Predicted ln substeps for n cells' features (device float32 in / out). */
+int chem_model_predict(chem_solver* s, int64_t n, const float* feats_dev, float* pred_dev,
+                       void* stream);
+/* Use given per-cell costs (device float32 [n_cells]) instead of the model's
+ * prediction for the next binned chem_integrate call on exactly n_cells cells
+ * (for comparison against bins sorted by true cost); NULL clears. */
+int chem_set_cost_override(chem_solver* s, int64_t n_cells, const float* cost_dev);
+/* Model state as a file: weights (FP32 master), normalisation, bin edges. */
+int chem_model_save(const chem_solver* s, const char* path);
+int chem_model_load(chem_solver* s, const char* path);
+/* Whether the last binned launch used the model (1) or fell back to queue
+ * order (0: no trained model, or a non-finite prediction). Host value. */
+int chem_last_binning_used(const chem_solver* s, int32_t* used);
+
+/* ---- autotuning --------------------------------------------------------- */
+
+/* Time the candidate launch shapes (cells per wave, waves per block, queue
+ * chunk) on n_sample cells (device [n_sample][2+Ns]) for the solver's current
+ * schedule and keep the fastest in the solver's options. Synchronises.
+ * Results are unaffected (the arithmetic per cell is the same for all
+ * shapes). */
+int chem_autotune(chem_solver* s, int64_t n_sample, const double* phi_sample_dev, double dt,
+                  void* stream);
+
+const char* chem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,312 @@
+"""Python binding of libchem.so (the C ABI in include/chem.h).
+
+Argument marshalling only: torch tensors provide device memory and the HIP
+stream; every step of the integration runs in the library's HIP kernels. The
+library must be built (``paper_2112_05834_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchem.so")
+
+PLAIN, PERSISTENT, PERSISTENT_BINNED = 0, 1, 2
+CELL_OK, CELL_MAX_STEPS, CELL_H_UNDERFLOW, CELL_NONFINITE, CELL_SINGULAR, CELL_T_RANGE = range(6)
+
+_ERRORS = {-1: "CHEM_EINVAL", -2: "CHEM_EMECH", -3: "CHEM_EHIP", -4: "CHEM_ENOMEM", -5: "CHEM_ESTATE",
+           -6: "CHEM_EUNSUPPORTED"}
+
+
+class ChemError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("max_steps", ctypes.c_int32),
+                ("schedule", ctypes.c_int32), ("cells_per_wave", ctypes.c_int32),
+                ("queue_chunk", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Load libchem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libchem.so is not built: run paper_2112_05834_amd.build.build() "
+                              "(hipcc, gfx950) first")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        sig = {
+            "chem_opts_default": (None, [ctypes.POINTER(Opts)]),
+            "chem_mech_load": (i32, [ctypes.c_char_p, ctypes.POINTER(_vp)]),
+            "chem_mech_dims": (i32, [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+            "chem_mech_work": (i32, [_vp] + [ctypes.POINTER(dbl)] * 4),
+            "chem_mech_free": (None, [_vp]),
+            "chem_solver_create": (i32, [_vp, ctypes.POINTER(Opts), i32, ctypes.POINTER(_vp)]),
+            "chem_solver_free": (None, [_vp]),
+            "chem_solver_set_opts": (i32, [_vp, ctypes.POINTER(Opts)]),
+            "chem_solver_get_opts": (i32, [_vp, ctypes.POINTER(Opts)]),
+            "chem_integrate": (i32, [_vp, i64, dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "chem_integrate_steps": (i32, [_vp, i32, i64, dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "chem_eval_rhs_jac": (i32, [_vp, i64, _vp, _vp, _vp, _vp]),
+            "chem_lu_batch": (i32, [_vp, i64, _vp, _vp, _vp, _vp, _vp]),
+            "chem_log_enable": (i32, [_vp, i64]),
+            "chem_log_fetch": (i32, [_vp, _vp, _vp, ctypes.POINTER(i64), _vp]),
+            "chem_features": (i32, [_vp, i64, dbl, _vp, _vp, _vp]),
+            "chem_train_opts_default": (None, [ctypes.POINTER(TrainOpts)]),
+            "chem_model_train": (i32, [_vp, i64, _vp, _vp, ctypes.POINTER(TrainOpts), _vp]),
+            "chem_model_predict": (i32, [_vp, i64, _vp, _vp, _vp]),
+            "chem_set_cost_override": (i32, [_vp, i64, _vp]),
+            "chem_model_save": (i32, [_vp, ctypes.c_char_p]),
+            "chem_model_load": (i32, [_vp, ctypes.c_char_p]),
+            "chem_last_binning_used": (i32, [_vp, ctypes.POINTER(i32)]),
+            "chem_autotune": (i32, [_vp, i64, _vp, dbl, _vp]),
+            "chem_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise ChemError(rc, lib().chem_last_error().decode())
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().chem_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def default_train_opts(**kw) -> TrainOpts:
+    t = TrainOpts()
+    lib().chem_train_opts_default(ctypes.byref(t))
+    for k, v in kw.items():
+        setattr(t, k, v)
+    return t
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=None, device=None, numel=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if device is not None and t.device != device:
+        raise ValueError("%s must be on %s, got %s" % (name, device, t.device))
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must have %d elements, got %d" % (name, numel, t.numel()))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Mechanism:
+    """A parsed mechanism (host side)."""
+
+    def __init__(self, path: str):
+        h = _vp()
+        _check(lib().chem_mech_load(path.encode(), ctypes.byref(h)))
+        self._h = h
+        ns, nr = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().chem_mech_dims(h, ctypes.byref(ns), ctypes.byref(nr)))
+        self.n_species, self.n_reactions = ns.value, nr.value
+        self.n = self.n_species + 1
+
+    def work(self):
+        v = [ctypes.c_double() for _ in range(4)]
+        _check(lib().chem_mech_work(self._h, *[ctypes.byref(x) for x in v]))
+        return {"flops_rhs": v[0].value, "flops_jac": v[1].value, "trans_rhs": v[2].value,
+                "trans_jac": v[3].value}
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.chem_mech_free(self._h)
+            self._h = None
+
+
+@dataclasses.dataclass
+class Result:
+    phi: torch.Tensor
+    h: Optional[torch.Tensor]
+    n_acc: torch.Tensor
+    n_rej: torch.Tensor
+    status: torch.Tensor
+
+
+class Solver:
+    """Integrator bound to one HIP device."""
+
+    def __init__(self, mech: Mechanism, opts: Optional[Opts] = None, device: int = 0):
+        self.mech = mech
+        self.device = torch.device("cuda", device)
+        h = _vp()
+        o = opts if opts is not None else default_opts()
+        _check(lib().chem_solver_create(mech._h, ctypes.byref(o), int(device), ctypes.byref(h)))
+        self._h = h
+        self.ns = mech.n_species
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.chem_solver_free(self._h)
+            self._h = None
+
+    @property
+    def opts(self) -> Opts:
+        o = Opts()
+        _check(lib().chem_solver_get_opts(self._h, ctypes.byref(o)))
+        return o
+
+    def set_opts(self, o: Opts = None, **kw):
+        o = o if o is not None else self.opts
+        for k, v in kw.items():
+            setattr(o, k, v)
+        _check(lib().chem_solver_set_opts(self._h, ctypes.byref(o)))
+
+    def _outs(self, n, h_io, out):
+        """h_io: a float64 tensor (in/out), None (start every cell at dt and
+        return the proposals in a new tensor) or False (not kept: NULL)."""
+        dev = self.device
+        phi_out = out if out is not None else torch.empty((n, self.ns + 2), dtype=torch.float64, device=dev)
+        if h_io is False:
+            h = None
+        else:
+            h = h_io if h_io is not None else torch.zeros(n, dtype=torch.float64, device=dev)
+        na = torch.empty(n, dtype=torch.int32, device=dev)
+        nr = torch.empty(n, dtype=torch.int32, device=dev)
+        st = torch.empty(n, dtype=torch.int8, device=dev)
+        return phi_out, h, na, nr, st
+
+    def integrate(self, phi: torch.Tensor, dt: float, h_io: Optional[torch.Tensor] = None,
+                  out: Optional[torch.Tensor] = None) -> Result:
+        """One chemistry step for every cell of phi ([n, 2+Ns] float64 on the
+        solver's device). h_io (if given) is updated in place."""
+        n = phi.shape[0]
+        if phi.dim() != 2 or phi.shape[1] != self.ns + 2:
+            raise ValueError("phi must be [n, %d]" % (self.ns + 2))
+        phi_out, h, na, nr, st = self._outs(n, h_io, out)
+        _check(lib().chem_integrate(self._h, n, float(dt),
+                                    _ptr(phi, torch.float64, self.device, name="phi"),
+                                    _ptr(phi_out, torch.float64, self.device, n * (self.ns + 2), "out"),
+                                    _ptr(h, torch.float64, self.device, n, "h_io"),
+                                    _ptr(na), _ptr(nr), _ptr(st), _stream(self.device)))
+        return Result(phi_out, h, na, nr, st)
+
+    def integrate_steps(self, phi: torch.Tensor, dt: float, n_steps: int,
+                        h_io: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None) -> Result:
+        n = phi.shape[0]
+        if phi.dim() != 2 or phi.shape[1] != self.ns + 2:
+            raise ValueError("phi must be [n, %d]" % (self.ns + 2))
+        phi_out, h, na, nr, st = self._outs(n, h_io, out)
+        _check(lib().chem_integrate_steps(self._h, int(n_steps), n, float(dt),
+                                          _ptr(phi, torch.float64, self.device, name="phi"),
+                                          _ptr(phi_out, torch.float64, self.device, n * (self.ns + 2), "out"),
+                                          _ptr(h, torch.float64, self.device, n, "h_io"),
+                                          _ptr(na), _ptr(nr), _ptr(st), _stream(self.device)))
+        return Result(phi_out, h, na, nr, st)
+
+    def eval_rhs_jac(self, phi: torch.Tensor, jac: bool = True):
+        n = phi.shape[0]
+        nn = self.ns + 1
+        f = torch.empty((n, nn), dtype=torch.float64, device=self.device)
+        J = torch.empty((n, nn, nn), dtype=torch.float64, device=self.device) if jac else None
+        _check(lib().chem_eval_rhs_jac(self._h, n, _ptr(phi, torch.float64, self.device, name="phi"),
+                                       _ptr(f), _ptr(J), _stream(self.device)))
+        return f, J
+
+    def lu_batch(self, A: torch.Tensor, b: Optional[torch.Tensor] = None):
+        """In-place batched LU of A [batch, n, n] (and solve of b [batch, n])."""
+        batch = A.shape[0]
+        nn = self.ns + 1
+        piv = torch.empty((batch, nn), dtype=torch.int32, device=self.device)
+        info = torch.empty(batch, dtype=torch.int32, device=self.device)
+        _check(lib().chem_lu_batch(self._h, batch, _ptr(A, torch.float64, self.device, batch * nn * nn, "A"),
+                                   _ptr(piv), _ptr(info),
+                                   _ptr(b, torch.float64, self.device, batch * nn, "b"), _stream(self.device)))
+        return A, piv, info, b
+
+    # ---- learned cost model ----
+    def log_enable(self, capacity: int):
+        _check(lib().chem_log_enable(self._h, int(capacity)))
+
+    def log_fetch(self, capacity: int):
+        f = torch.empty((capacity, 4), dtype=torch.float32, device=self.device)
+        t = torch.empty(capacity, dtype=torch.float32, device=self.device)
+        n = ctypes.c_int64()
+        _check(lib().chem_log_fetch(self._h, _ptr(f), _ptr(t), ctypes.byref(n), _stream(self.device)))
+        return f[:n.value], t[:n.value]
+
+    def features(self, phi: torch.Tensor, dt: float) -> torch.Tensor:
+        n = phi.shape[0]
+        f = torch.empty((n, 4), dtype=torch.float32, device=self.device)
+        _check(lib().chem_features(self._h, n, float(dt), _ptr(phi, torch.float64, self.device, name="phi"),
+                                   _ptr(f), _stream(self.device)))
+        return f
+
+    def model_train(self, feats: torch.Tensor, target: torch.Tensor, opts: Optional[TrainOpts] = None):
+        n = feats.shape[0]
+        t = opts if opts is not None else default_train_opts()
+        _check(lib().chem_model_train(self._h, n, _ptr(feats, torch.float32, self.device, 4 * n, "feats"),
+                                      _ptr(target, torch.float32, self.device, n, "target"), ctypes.byref(t),
+                                      _stream(self.device)))
+
+    def model_predict(self, feats: torch.Tensor) -> torch.Tensor:
+        n = feats.shape[0]
+        out = torch.empty(n, dtype=torch.float32, device=self.device)
+        _check(lib().chem_model_predict(self._h, n, _ptr(feats, torch.float32, self.device, 4 * n, "feats"),
+                                        _ptr(out), _stream(self.device)))
+        return out
+
+    def set_cost_override(self, cost: Optional[torch.Tensor]):
+        if cost is None:
+            _check(lib().chem_set_cost_override(self._h, 0, None))
+        else:
+            _check(lib().chem_set_cost_override(self._h, cost.numel(),
+                                                _ptr(cost, torch.float32, self.device, name="cost")))
+        self._cost_ref = cost
+
+    def model_save(self, path: str):
+        _check(lib().chem_model_save(self._h, path.encode()))
+
+    def model_load(self, path: str):
+        _check(lib().chem_model_load(self._h, path.encode()))
+
+    def last_binning_used(self) -> bool:
+        u = ctypes.c_int32()
+        _check(lib().chem_last_binning_used(self._h, ctypes.byref(u)))
+        return bool(u.value)
+
+    def autotune(self, phi_sample: torch.Tensor, dt: float):
+        _check(lib().chem_autotune(self._h, phi_sample.shape[0],
+                                   _ptr(phi_sample, torch.float64, self.device, name="phi"), float(dt),
+                                   _stream(self.device)))

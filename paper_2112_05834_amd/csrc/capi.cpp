@@ -1,0 +1,676 @@
+// C ABI of the stiff-chemistry integrator: argument checking, launch shape
+// selection, the persistent work queue, chained steps in a HIP graph, and
+// the learned cost model driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/chem.h"
+#include "kernels.hpp"
+#include "mech.hpp"
+#include "model.hpp"
+
+struct chem_mech {
+  chem::MechHost host;
+  chem::Packed packed;
+  chem::Work work;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return CHEM_EHIP;
+}
+
+#define HIP_TRY(expr, what)                 \
+  do {                                      \
+    hipError_t _e = (expr);                 \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    hipGetDevice(&prev);
+    if (prev != dev) hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    hipGetDevice(&cur);
+    if (prev >= 0 && cur != prev) hipSetDevice(prev);
+  }
+};
+
+constexpr size_t kMaxLds = 160 * 1024;
+
+}  // namespace
+
+struct chem_solver {
+  int dev = 0;
+  int cus = 0;
+  chem_opts opts{};
+  int ns = 0, nr = 0, n = 0;
+  chemk::MechArgs margs{};
+  void* d_blob = nullptr;
+  double* d_nasa = nullptr;
+  double* d_W = nullptr;
+  unsigned long long* d_head = nullptr;   // [0] queue head, [1] log head
+  chemk::Variant variants[8];
+  int nvariants = 0;
+  chem::Work work{};
+  // chained steps
+  double* d_ping = nullptr;
+  size_t ping_cells = 0;
+  hipGraphExec_t graph = nullptr;
+  hipGraph_t graph_src = nullptr;
+  hipStream_t capture_stream = nullptr;   // graphs are captured here, launched on the caller's stream
+  struct {
+    int32_t n_steps = 0;
+    int64_t n_cells = 0;
+    double dt = 0;
+    const void *in = nullptr, *out = nullptr, *h = nullptr, *a = nullptr, *r = nullptr, *s = nullptr;
+    hipStream_t st = nullptr;
+    chem_opts o{};
+  } gkey;
+  // learned cost model and binning
+  chem_model::Model model;
+  int last_binning_used = 0;
+  const float* cost_override = nullptr;
+  int64_t cost_override_n = 0;
+  // logging
+  float* log_feats = nullptr;
+  float* log_target = nullptr;
+  int64_t log_cap = 0;
+};
+
+extern "C" {
+
+const char* chem_last_error(void) { return g_err.c_str(); }
+
+void chem_opts_default(chem_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->rtol = 1e-6;
+  o->atol = 1e-10;
+  o->max_steps = 100000;
+  o->schedule = CHEM_PLAIN;
+}
+
+int chem_mech_load(const char* path, chem_mech** out) {
+  if (!path || !out) return fail(CHEM_EINVAL, "chem_mech_load: null argument");
+  *out = nullptr;
+  auto m = std::make_unique<chem_mech>();
+  std::string err;
+  if (!chem::parse_mechanism(path, m->host, err)) return fail(CHEM_EMECH, err);
+  m->packed = chem::pack(m->host);
+  m->work = chem::count_work(m->host);
+  *out = m.release();
+  return CHEM_OK;
+}
+
+int chem_mech_dims(const chem_mech* m, int32_t* ns, int32_t* nr) {
+  if (!m) return fail(CHEM_EINVAL, "chem_mech_dims: null mechanism");
+  if (ns) *ns = m->host.ns;
+  if (nr) *nr = m->host.nr;
+  return CHEM_OK;
+}
+
+int chem_mech_work(const chem_mech* m, double* f_rhs, double* f_jac, double* t_rhs, double* t_jac) {
+  if (!m) return fail(CHEM_EINVAL, "chem_mech_work: null mechanism");
+  if (f_rhs) *f_rhs = m->work.f_rhs;
+  if (f_jac) *f_jac = m->work.f_jac;
+  if (t_rhs) *t_rhs = m->work.t_rhs;
+  if (t_jac) *t_jac = m->work.t_jac;
+  return CHEM_OK;
+}
+
+void chem_mech_free(chem_mech* m) { delete m; }
+
+static int check_opts(const chem_opts* o) {
+  if (!o) return fail(CHEM_EINVAL, "null options");
+  if (!(o->rtol > 0) || !(o->atol > 0) || !std::isfinite(o->rtol) || !std::isfinite(o->atol))
+    return fail(CHEM_EINVAL, "rtol and atol must be positive and finite");
+  if (o->max_steps < 1) return fail(CHEM_EINVAL, "max_steps must be >= 1");
+  if (o->schedule < CHEM_PLAIN || o->schedule > CHEM_PERSISTENT_BINNED)
+    return fail(CHEM_EINVAL, "unknown schedule");
+  if (o->cells_per_wave < 0 || o->cells_per_wave > 8 || (o->cells_per_wave & (o->cells_per_wave - 1)))
+    return fail(CHEM_EINVAL, "cells_per_wave must be 0, 1, 2, 4 or 8");
+  if (o->queue_chunk < 0 || o->blocks < 0 || o->waves_per_block < 0 || o->waves_per_block > 4 ||
+      o->hbm_budget_bytes < 0)
+    return fail(CHEM_EINVAL, "negative launch option or waves_per_block > 4");
+  return CHEM_OK;
+}
+
+int chem_solver_create(const chem_mech* m, const chem_opts* o, int32_t dev, chem_solver** out) {
+  if (!m || !out) return fail(CHEM_EINVAL, "chem_solver_create: null argument");
+  *out = nullptr;
+  chem_opts def;
+  chem_opts_default(&def);
+  if (!o) o = &def;
+  if (int rc = check_opts(o)) return rc;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+  if (dev < 0 || dev >= ndev) return fail(CHEM_EINVAL, "hip_device out of range");
+  auto s = std::make_unique<chem_solver>();
+  s->dev = dev;
+  s->opts = *o;
+  s->ns = m->host.ns;
+  s->nr = m->host.nr;
+  s->n = s->ns + 1;
+  s->work = m->work;
+  s->nvariants = chemk::variants_for(s->n, s->variants, 8);
+  if (s->nvariants == 0)
+    return fail(CHEM_EUNSUPPORTED, "no compiled kernel for state size " + std::to_string(s->n));
+  DeviceGuard g(dev);
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+  s->cus = prop.multiProcessorCount;
+  const chem::Packed& P = m->packed;
+  HIP_TRY(hipMalloc(&s->d_blob, P.blob.size()), "hipMalloc");
+  HIP_TRY(hipMemcpy(s->d_blob, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(hipMalloc(&s->d_nasa, P.nasa.size() * sizeof(double)), "hipMalloc");
+  HIP_TRY(hipMemcpy(s->d_nasa, P.nasa.data(), P.nasa.size() * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(hipMalloc(&s->d_W, P.W.size() * sizeof(double)), "hipMalloc");
+  HIP_TRY(hipMemcpy(s->d_W, P.W.data(), P.W.size() * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(hipMalloc(&s->d_head, 4 * sizeof(unsigned long long)), "hipMalloc");
+  HIP_TRY(hipMemset(s->d_head, 0, 4 * sizeof(unsigned long long)), "hipMemset");
+  chemk::MechArgs& a = s->margs;
+  a.ns = s->ns;
+  a.nr = s->nr;
+  a.off_lnA = P.off_lnA;
+  a.off_b = P.off_b;
+  a.off_EaR = P.off_EaR;
+  a.off_rint = P.off_rint;
+  a.off_troe = P.off_troe;
+  a.off_eff_sp = P.off_eff_sp;
+  a.off_eff_am1 = P.off_eff_am1;
+  a.off_sp_off = P.off_sp_off;
+  a.off_sp_ent = P.off_sp_ent;
+  a.off_rW = P.off_rW;
+  a.blob_bytes = static_cast<int>(P.blob.size());
+  a.lds_bytes = P.lds_bytes;
+  a.blob = static_cast<const uint4*>(s->d_blob);
+  a.nasa = s->d_nasa;
+  a.W = s->d_W;
+  if (int rc = chem_model::init(s->model)) return fail(rc, chem_model::last_error());
+  HIP_TRY(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
+  *out = s.release();
+  return CHEM_OK;
+}
+
+static void drop_graph(chem_solver* s) {
+  if (s->graph) hipGraphExecDestroy(s->graph);
+  if (s->graph_src) hipGraphDestroy(s->graph_src);
+  s->graph = nullptr;
+  s->graph_src = nullptr;
+  s->gkey.n_steps = 0;
+}
+
+void chem_solver_free(chem_solver* s) {
+  if (!s) return;
+  DeviceGuard g(s->dev);
+  hipDeviceSynchronize();
+  drop_graph(s);
+  chem_model::release(s->model);
+  hipFree(s->d_blob);
+  hipFree(s->d_nasa);
+  hipFree(s->d_W);
+  hipFree(s->d_head);
+  hipFree(s->d_ping);
+  hipFree(s->log_feats);
+  hipFree(s->log_target);
+  if (s->capture_stream) hipStreamDestroy(s->capture_stream);
+  delete s;
+}
+
+int chem_solver_set_opts(chem_solver* s, const chem_opts* o) {
+  if (!s) return fail(CHEM_EINVAL, "null solver");
+  if (int rc = check_opts(o)) return rc;
+  s->opts = *o;
+  return CHEM_OK;
+}
+
+int chem_solver_get_opts(const chem_solver* s, chem_opts* o) {
+  if (!s || !o) return fail(CHEM_EINVAL, "null argument");
+  *o = s->opts;
+  return CHEM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// launch shape
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Shape {
+  chemk::Variant v;
+  int wpb = 4;
+  int cpw = 1;
+  size_t lds = 0;
+};
+
+int pick_shape(const chem_solver* s, const chem_opts& o, Shape& sh) {
+  // variant by requested cells per wave, else the first compiled one
+  int want_g = o.cells_per_wave > 0 ? 64 / o.cells_per_wave : 0;
+  sh.v = s->variants[0];
+  if (want_g) {
+    bool found = false;
+    for (int i = 0; i < s->nvariants; ++i)
+      if (s->variants[i].g == want_g) {
+        sh.v = s->variants[i];
+        found = true;
+      }
+    if (!found)
+      return fail(CHEM_EUNSUPPORTED, "cells_per_wave " + std::to_string(o.cells_per_wave) +
+                                         " not compiled for state size " + std::to_string(s->n));
+  }
+  sh.cpw = 64 / sh.v.g;
+  const size_t cell_bytes = sizeof(double) * chemk::cell_doubles(sh.v.nn, s->nr, s->ns);
+  const size_t blob = s->margs.lds_bytes;
+  int wpb = o.waves_per_block > 0 ? o.waves_per_block : 4;
+  while (wpb > 1 && blob + wpb * sh.cpw * cell_bytes > kMaxLds) --wpb;
+  sh.lds = blob + wpb * sh.cpw * cell_bytes;
+  if (sh.lds > kMaxLds)
+    return fail(CHEM_EUNSUPPORTED, "mechanism and one cell's work area exceed the 160 KB LDS");
+  sh.wpb = wpb;
+  return CHEM_OK;
+}
+
+int check_integrate_args(const chem_solver* s, int64_t n, double dt, const double* in, double* out) {
+  if (!s) return fail(CHEM_EINVAL, "null solver");
+  if (n < 0) return fail(CHEM_EINVAL, "n_cells < 0");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(CHEM_EINVAL, "dt must be positive and finite");
+  if (n > 0 && (!in || !out)) return fail(CHEM_EINVAL, "null phi_in or phi_out");
+  if (n > 0 && in != out) {
+    const char* a = reinterpret_cast<const char*>(in);
+    const char* b = reinterpret_cast<const char*>(out);
+    const size_t bytes = static_cast<size_t>(n) * (s->ns + 2) * sizeof(double);
+    if (a < b + bytes && b < a + bytes) return fail(CHEM_EINVAL, "phi_in and phi_out overlap partially");
+  }
+  return CHEM_OK;
+}
+
+// One chemistry step with the solver's options on stream st.
+int launch_step(chem_solver* s, const chem_opts& o, int64_t n, double dt, const double* in, double* out,
+                double* h_io, int32_t* n_acc, int32_t* n_rej, int8_t* status, int accumulate,
+                const int* perm, hipStream_t st) {
+  Shape sh;
+  if (int rc = pick_shape(s, o, sh)) return rc;
+  chemk::IntegrateArgs a{};
+  a.m = s->margs;
+  a.o.rtol = o.rtol;
+  a.o.atol = o.atol;
+  a.o.max_steps = o.max_steps;
+  a.dt = dt;
+  a.n = n;
+  a.phi_in = in;
+  a.phi_out = out;
+  a.h_io = h_io;
+  a.n_acc = n_acc;
+  a.n_rej = n_rej;
+  a.status = reinterpret_cast<signed char*>(status);
+  a.accumulate = accumulate;
+  a.cell_doubles = chemk::cell_doubles(sh.v.nn, s->nr, s->ns);
+  a.wpb = sh.wpb;
+  a.perm = perm;
+  a.head = s->d_head;
+  a.chunk = o.queue_chunk > 0 ? o.queue_chunk : 1;
+  a.log.cap = s->log_cap;
+  a.log.feats = s->log_feats;
+  a.log.target = s->log_target;
+  a.log.head = s->d_head + 1;
+  const bool persistent = o.schedule != CHEM_PLAIN;
+  const long long per_block = static_cast<long long>(sh.wpb) * sh.cpw;
+  long long grid;
+  if (!persistent) {
+    grid = (n + per_block - 1) / per_block;
+  } else {
+    int bpc = chemk::integrate_blocks_per_cu(sh.v, true, sh.wpb, sh.lds);
+    if (bpc < 1) bpc = 1;
+    grid = o.blocks > 0 ? o.blocks : static_cast<long long>(s->cus) * bpc;
+    const long long need = (n + per_block - 1) / per_block;
+    if (grid > need) grid = need;
+    HIP_TRY(chemk::launch_fill_u64(s->d_head, 0ull, st), "queue reset");
+  }
+  if (grid < 1) return CHEM_OK;
+  if (grid > 0x7fffffffLL) return fail(CHEM_EINVAL, "too many cells for one launch");
+  HIP_TRY(chemk::launch_integrate(sh.v, persistent, static_cast<int>(grid), a, sh.lds, st), "integrate launch");
+  return CHEM_OK;
+}
+
+int binned_perm(chem_solver* s, int64_t n, double dt, const double* in, hipStream_t st, const int** perm) {
+  *perm = nullptr;
+  int used = 0;
+  const float* over = (s->cost_override && s->cost_override_n == n) ? s->cost_override : nullptr;
+  int rc = chem_model::plan(s->model, s->margs, s->nvariants ? s->variants[0] : chemk::Variant{0, 0}, n, dt, in,
+                            over, st, perm, &used);
+  if (rc) return fail(rc, chem_model::last_error());
+  s->last_binning_used = used;
+  return CHEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chem_integrate(chem_solver* s, int64_t n, double dt, const double* in, double* out, double* h_io,
+                   int32_t* n_acc, int32_t* n_rej, int8_t* status, void* stream) {
+  if (int rc = check_integrate_args(s, n, dt, in, out)) return rc;
+  if (n == 0) return CHEM_OK;
+  DeviceGuard g(s->dev);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int* perm = nullptr;
+  if (s->opts.schedule == CHEM_PERSISTENT_BINNED) {
+    if (int rc = binned_perm(s, n, dt, in, st, &perm)) return rc;
+  }
+  return launch_step(s, s->opts, n, dt, in, out, h_io, n_acc, n_rej, status, 0, perm, st);
+}
+
+int chem_integrate_steps(chem_solver* s, int32_t n_steps, int64_t n, double dt, const double* in, double* out,
+                         double* h_io, int32_t* n_acc, int32_t* n_rej, int8_t* status, void* stream) {
+  if (int rc = check_integrate_args(s, n, dt, in, out)) return rc;
+  if (n_steps < 1) return fail(CHEM_EINVAL, "n_steps must be >= 1");
+  if (n == 0) return CHEM_OK;
+  if (in == out && n_steps > 1) return fail(CHEM_EINVAL, "chem_integrate_steps: phi_in must not alias phi_out");
+  DeviceGuard g(s->dev);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t w = static_cast<size_t>(s->ns) + 2;
+  if (s->ping_cells < static_cast<size_t>(n) && n_steps > 1) {
+    drop_graph(s);
+    hipFree(s->d_ping);
+    s->d_ping = nullptr;
+    s->ping_cells = 0;
+    HIP_TRY(hipMalloc(&s->d_ping, static_cast<size_t>(n) * w * sizeof(double)), "hipMalloc ping buffer");
+    s->ping_cells = static_cast<size_t>(n);
+  }
+  auto& k = s->gkey;
+  const bool same = s->graph && k.n_steps == n_steps && k.n_cells == n && k.dt == dt && k.in == in && k.out == out &&
+                    k.h == h_io && k.a == n_acc && k.r == n_rej && k.s == status && k.st == st &&
+                    std::memcmp(&k.o, &s->opts, sizeof(chem_opts)) == 0;
+  if (!same) {
+    drop_graph(s);
+    hipStreamCaptureStatus cs;
+    HIP_TRY(hipStreamIsCapturing(st, &cs), "hipStreamIsCapturing");
+    const bool outer_capture = cs != hipStreamCaptureStatusNone;
+    if (outer_capture) {
+      // the caller is capturing already: enqueue the steps into its graph
+      goto enqueue_direct;
+    }
+    // capture on the solver's own stream (the caller's may be the null
+    // stream, which cannot be captured); the graph is launched on st
+    hipStream_t cst = s->capture_stream;
+    HIP_TRY(hipStreamBeginCapture(cst, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    {
+      int rc = CHEM_OK;
+      // step k reads src and writes dst; the last step writes out
+      for (int32_t step = 0; step < n_steps && rc == CHEM_OK; ++step) {
+        const double* src = step == 0 ? in : ((n_steps - step) % 2 == 0 ? out : s->d_ping);
+        double* dst = ((n_steps - 1 - step) % 2 == 0) ? out : s->d_ping;
+        const int* perm = nullptr;
+        if (s->opts.schedule == CHEM_PERSISTENT_BINNED) rc = binned_perm(s, n, dt, src, cst, &perm);
+        if (rc == CHEM_OK)
+          rc = launch_step(s, s->opts, n, dt, src, dst, h_io, n_acc, n_rej, status, step > 0, perm, cst);
+      }
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(cst, &graph);
+      if (rc != CHEM_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return rc;
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      hipGraphExec_t exec = nullptr;
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+      }
+      s->graph = exec;
+      s->graph_src = graph;
+      k.n_steps = n_steps;
+      k.n_cells = n;
+      k.dt = dt;
+      k.in = in;
+      k.out = out;
+      k.h = h_io;
+      k.a = n_acc;
+      k.r = n_rej;
+      k.s = status;
+      k.st = st;
+      k.o = s->opts;
+    }
+  }
+  HIP_TRY(hipGraphLaunch(s->graph, st), "hipGraphLaunch");
+  return CHEM_OK;
+
+enqueue_direct:
+  for (int32_t step = 0; step < n_steps; ++step) {
+    const double* src = step == 0 ? in : ((n_steps - step) % 2 == 0 ? out : s->d_ping);
+    double* dst = ((n_steps - 1 - step) % 2 == 0) ? out : s->d_ping;
+    const int* perm = nullptr;
+    if (s->opts.schedule == CHEM_PERSISTENT_BINNED)
+      if (int rc = binned_perm(s, n, dt, src, st, &perm)) return rc;
+    if (int rc = launch_step(s, s->opts, n, dt, src, dst, h_io, n_acc, n_rej, status, step > 0, perm, st)) return rc;
+  }
+  return CHEM_OK;
+}
+
+int chem_eval_rhs_jac(chem_solver* s, int64_t n, const double* phi, double* f, double* J, void* stream) {
+  if (!s || n < 0 || (n > 0 && (!phi || !f))) return fail(CHEM_EINVAL, "chem_eval_rhs_jac: bad argument");
+  if (n == 0) return CHEM_OK;
+  DeviceGuard g(s->dev);
+  chem_opts o = s->opts;
+  Shape sh;
+  if (int rc = pick_shape(s, o, sh)) return rc;
+  chemk::EvalArgs a{};
+  a.m = s->margs;
+  a.n = n;
+  a.phi = phi;
+  a.f = f;
+  a.J = J;
+  a.cell_doubles = chemk::cell_doubles(sh.v.nn, s->nr, s->ns);
+  a.wpb = sh.wpb;
+  const long long per_block = static_cast<long long>(sh.wpb) * sh.cpw;
+  const long long grid = (n + per_block - 1) / per_block;
+  HIP_TRY(chemk::launch_eval(sh.v, static_cast<int>(grid), a, sh.lds, static_cast<hipStream_t>(stream)), "eval launch");
+  return CHEM_OK;
+}
+
+int chem_lu_batch(chem_solver* s, int64_t batch, double* A, int32_t* piv, int32_t* info, double* b, void* stream) {
+  if (!s || batch < 0 || (batch > 0 && (!A || !piv || !info))) return fail(CHEM_EINVAL, "chem_lu_batch: bad argument");
+  if (batch == 0) return CHEM_OK;
+  DeviceGuard g(s->dev);
+  Shape sh;
+  if (int rc = pick_shape(s, s->opts, sh)) return rc;
+  chemk::LuArgs a{};
+  a.batch = batch;
+  a.n = s->n;
+  a.A = A;
+  a.piv = piv;
+  a.info = info;
+  a.b = b;
+  a.wpb = 4;
+  const long long per_block = 4LL * sh.cpw;
+  const long long grid = (batch + per_block - 1) / per_block;
+  HIP_TRY(chemk::launch_lu(sh.v, static_cast<int>(grid), a, static_cast<hipStream_t>(stream)), "lu launch");
+  return CHEM_OK;
+}
+
+// ---- learned cost model --------------------------------------------------
+
+int chem_log_enable(chem_solver* s, int64_t cap) {
+  if (!s || cap < 0) return fail(CHEM_EINVAL, "chem_log_enable: bad argument");
+  DeviceGuard g(s->dev);
+  hipFree(s->log_feats);
+  hipFree(s->log_target);
+  s->log_feats = nullptr;
+  s->log_target = nullptr;
+  s->log_cap = 0;
+  drop_graph(s);
+  if (cap == 0) return CHEM_OK;
+  HIP_TRY(hipMalloc(&s->log_feats, static_cast<size_t>(cap) * 4 * sizeof(float)), "hipMalloc log");
+  HIP_TRY(hipMalloc(&s->log_target, static_cast<size_t>(cap) * sizeof(float)), "hipMalloc log");
+  HIP_TRY(hipMemset(s->d_head + 1, 0, sizeof(unsigned long long)), "hipMemset");
+  s->log_cap = cap;
+  return CHEM_OK;
+}
+
+int chem_log_fetch(chem_solver* s, float* feats, float* target, int64_t* n_out, void* stream) {
+  if (!s || !n_out) return fail(CHEM_EINVAL, "chem_log_fetch: bad argument");
+  DeviceGuard g(s->dev);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  unsigned long long cnt = 0;
+  HIP_TRY(hipMemcpy(&cnt, s->d_head + 1, sizeof(cnt), hipMemcpyDeviceToHost), "hipMemcpy");
+  const int64_t nv = s->log_cap == 0 ? 0 : static_cast<int64_t>(std::min<unsigned long long>(cnt, s->log_cap));
+  if (nv > 0 && (!feats || !target)) return fail(CHEM_EINVAL, "chem_log_fetch: null output buffer");
+  if (nv > 0) {
+    HIP_TRY(hipMemcpy(feats, s->log_feats, nv * 4 * sizeof(float), hipMemcpyDeviceToDevice), "hipMemcpy");
+    HIP_TRY(hipMemcpy(target, s->log_target, nv * sizeof(float), hipMemcpyDeviceToDevice), "hipMemcpy");
+  }
+  *n_out = nv;
+  return CHEM_OK;
+}
+
+int chem_features(chem_solver* s, int64_t n, double dt, const double* phi, float* feats, void* stream) {
+  if (!s || n < 0 || (n > 0 && (!phi || !feats)) || !(dt > 0)) return fail(CHEM_EINVAL, "chem_features: bad argument");
+  if (n == 0) return CHEM_OK;
+  DeviceGuard g(s->dev);
+  int rc = chem_model::features(s->margs, n, dt, phi, feats, static_cast<hipStream_t>(stream));
+  return rc ? fail(rc, chem_model::last_error()) : CHEM_OK;
+}
+
+void chem_train_opts_default(chem_train_opts* t) {
+  if (!t) return;
+  t->epochs = 10;
+  t->batch = 4096;
+  t->lr = 1e-3f;
+  t->beta1 = 0.9f;
+  t->beta2 = 0.999f;
+  t->eps = 1e-8f;
+  t->seed = 1234;
+}
+
+int chem_model_train(chem_solver* s, int64_t n, const float* feats, const float* target, const chem_train_opts* t,
+                     void* stream) {
+  if (!s || n < 1 || !feats || !target) return fail(CHEM_EINVAL, "chem_model_train: bad argument");
+  chem_train_opts def;
+  chem_train_opts_default(&def);
+  if (!t) t = &def;
+  if (t->epochs < 1 || t->batch < 1 || !(t->lr > 0)) return fail(CHEM_EINVAL, "chem_model_train: bad options");
+  DeviceGuard g(s->dev);
+  drop_graph(s);
+  int rc = chem_model::train(s->model, n, feats, target, *t, static_cast<hipStream_t>(stream));
+  return rc ? fail(rc, chem_model::last_error()) : CHEM_OK;
+}
+
+int chem_model_predict(chem_solver* s, int64_t n, const float* feats, float* pred, void* stream) {
+  if (!s || n < 0 || (n > 0 && (!feats || !pred))) return fail(CHEM_EINVAL, "chem_model_predict: bad argument");
+  if (n == 0) return CHEM_OK;
+  DeviceGuard g(s->dev);
+  int rc = chem_model::predict(s->model, n, feats, pred, static_cast<hipStream_t>(stream));
+  return rc ? fail(rc, chem_model::last_error()) : CHEM_OK;
+}
+
+int chem_set_cost_override(chem_solver* s, int64_t n, const float* cost) {
+  if (!s || (cost && n < 1)) return fail(CHEM_EINVAL, "chem_set_cost_override: bad argument");
+  s->cost_override = cost;
+  s->cost_override_n = cost ? n : 0;
+  drop_graph(s);
+  return CHEM_OK;
+}
+
+int chem_model_save(const chem_solver* s, const char* path) {
+  if (!s || !path) return fail(CHEM_EINVAL, "chem_model_save: bad argument");
+  DeviceGuard g(s->dev);
+  int rc = chem_model::save(s->model, path);
+  return rc ? fail(rc, chem_model::last_error()) : CHEM_OK;
+}
+
+int chem_model_load(chem_solver* s, const char* path) {
+  if (!s || !path) return fail(CHEM_EINVAL, "chem_model_load: bad argument");
+  DeviceGuard g(s->dev);
+  drop_graph(s);
+  int rc = chem_model::load(s->model, path);
+  return rc ? fail(rc, chem_model::last_error()) : CHEM_OK;
+}
+
+int chem_last_binning_used(const chem_solver* s, int32_t* used) {
+  if (!s || !used) return fail(CHEM_EINVAL, "chem_last_binning_used: bad argument");
+  *used = s->last_binning_used;
+  return CHEM_OK;
+}
+
+// ---- autotuning ------------------------------------------------------------
+
+int chem_autotune(chem_solver* s, int64_t n_sample, const double* phi, double dt, void* stream) {
+  if (!s || n_sample < 1 || !phi || !(dt > 0)) return fail(CHEM_EINVAL, "chem_autotune: bad argument");
+  DeviceGuard g(s->dev);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t w = static_cast<size_t>(s->ns) + 2;
+  double* out = nullptr;
+  double* h = nullptr;
+  HIP_TRY(hipMalloc(&out, n_sample * w * sizeof(double)), "hipMalloc");
+  HIP_TRY(hipMalloc(&h, n_sample * sizeof(double)), "hipMalloc");
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  chem_opts best = s->opts;
+  float best_ms = 1e30f;
+  int rc = CHEM_OK;
+  const int chunks[] = {1, 2, 4, 8};
+  for (int vi = 0; vi < s->nvariants && rc == CHEM_OK; ++vi) {
+    for (int wpb = 1; wpb <= 4 && rc == CHEM_OK; wpb *= 2) {
+      for (int ci = 0; ci < (s->opts.schedule == CHEM_PLAIN ? 1 : 4) && rc == CHEM_OK; ++ci) {
+        chem_opts o = s->opts;
+        o.cells_per_wave = 64 / s->variants[vi].g;
+        o.waves_per_block = wpb;
+        o.queue_chunk = chunks[ci];
+        Shape sh;
+        if (pick_shape(s, o, sh) != CHEM_OK || sh.wpb != wpb) continue;
+        float ms = 0;
+        for (int rep = 0; rep < 2; ++rep) {   // first repetition warms up
+          hipMemsetAsync(h, 0, n_sample * sizeof(double), st);
+          hipEventRecord(e0, st);
+          rc = launch_step(s, o, n_sample, dt, phi, out, h, nullptr, nullptr, nullptr, 0, nullptr, st);
+          hipEventRecord(e1, st);
+          if (rc) break;
+          if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(CHEM_EHIP, "autotune: launch failed");
+            break;
+          }
+          hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (rc == CHEM_OK && ms < best_ms) {
+          best_ms = ms;
+          best = o;
+        }
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(out);
+  hipFree(h);
+  if (rc) return rc;
+  best.blocks = s->opts.blocks;
+  s->opts = best;
+  drop_graph(s);
+  return CHEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1026 @@
+// Per-cell stiff chemistry integration on CDNA4 (gfx950).
+//
+// One cell is owned by a group of G lanes of a 64-wide wavefront (G = 64: one
+// cell per wave; G = 16: four cells per wave), with G >= n = Ns + 1. Lane i
+// of the group owns state component i (0 = T, 1..Ns = Y_1..Y_Ns) and row i of
+// the Rosenbrock matrix M = I/(gamma h) - J, kept in registers. The analytical
+// Jacobian is assembled row-wise in the group's LDS area, from the mechanism
+// image that every block stages in LDS; it stays there across rejected steps.
+//
+// Arithmetic per cell does not depend on G, on the cell's position in the
+// grid or on the schedule: reductions follow one fixed pairing tree over 64
+// virtual lanes, pivots are chosen by value then lowest position, and every
+// other operation is per element in a fixed order.
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace chemk {
+
+namespace {
+
+constexpr double kR = 8.314462618;     // J mol^-1 K^-1
+constexpr double kPatm = 101325.0;     // Pa
+constexpr double kLn10 = 2.302585092994045684;
+constexpr int kBig = 1 << 20;
+
+// Rodas3 in the transformed form (unknowns u_i, matrix I/(gamma h) - J):
+// u_s = M^-1 ( f(y + sum_j a_sj u_j) + sum_j (c_sj / h) u_j ), y_new = y + sum m_j u_j,
+// error estimate u_4.
+constexpr double kGamma = 0.5;
+constexpr double kA31 = 2.0, kA41 = 2.0, kA43 = 1.0;
+constexpr double kC21 = 4.0, kC31 = 1.0, kC32 = -1.0, kC41 = 1.0, kC42 = -1.0;
+constexpr double kC43 = -8.0 / 3.0;
+// step-size controller
+constexpr double kFacMin = 0.2, kFacMax = 6.0, kFacSafe = 0.9, kFacRej = 0.1;
+constexpr double kHMin = 1e-20, kTMin = 200.0, kTMax = 6000.0;
+
+// LDS accesses of one wave stay ordered; keep the compiler from moving them
+// across a point where other lanes' writes must be visible.
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// LDS add whose result is not returned: nothing waits on it
+__device__ __forceinline__ void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// ---------------------------------------------------------------------------
+// lane-group primitives (one cell per group of G lanes, G in {16, 32, 64})
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+constexpr int kXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kHalfMirror = 0x141; // lane i <-> 7-i within 8
+constexpr int kMirror = 0x140;     // lane i <-> 15-i within 16
+
+template <int G>
+struct Grp {
+  static_assert(G == 16 || G == 32 || G == 64, "group width");
+  __device__ static __forceinline__ int lane() { return static_cast<int>(__lane_id()); }
+  __device__ static __forceinline__ int gl() { return lane() & (G - 1); }
+  __device__ static __forceinline__ int base() { return lane() & ~(G - 1); }
+
+  // value of v in group lane src (src equal across the group)
+  __device__ static __forceinline__ double bcast(double v, int src) {
+    if constexpr (G == 64) {
+      return readlane_d(v, __builtin_amdgcn_readfirstlane(src));
+    } else {
+      return __shfl(v, base() + src, 64);
+    }
+  }
+  __device__ static __forceinline__ int bcast_i(int v, int src) {
+    if constexpr (G == 64) {
+      return __builtin_amdgcn_readlane(v, __builtin_amdgcn_readfirstlane(src));
+    } else {
+      return __shfl(v, base() + src, 64);
+    }
+  }
+  // Sum over the 64 virtual lanes of a cell (lanes beyond the group add +0)
+  // with one pairing tree for every G: xor 1, xor 2, then the 8-lane and
+  // 16-lane mirrors inside a DPP row, then rows (0+1) + (2+3).
+  __device__ static __forceinline__ double sum(double x) {
+    x = x + dpp_d<kXor1>(x);
+    x = x + dpp_d<kXor2>(x);
+    x = x + dpp_d<kHalfMirror>(x);
+    x = x + dpp_d<kMirror>(x);
+    if constexpr (G == 64) {
+      const double r0 = readlane_d(x, 0), r1 = readlane_d(x, 16);
+      const double r2 = readlane_d(x, 32), r3 = readlane_d(x, 48);
+      return (r0 + r1) + (r2 + r3);
+    } else if constexpr (G == 32) {
+      return (x + __shfl_xor(x, 16, 64)) + (0.0 + 0.0);
+    } else {
+      return (x + 0.0) + (0.0 + 0.0);
+    }
+  }
+  __device__ static __forceinline__ double max(double x) {
+    x = fmax(x, dpp_d<kXor1>(x));
+    x = fmax(x, dpp_d<kXor2>(x));
+    x = fmax(x, dpp_d<kHalfMirror>(x));
+    x = fmax(x, dpp_d<kMirror>(x));
+    if constexpr (G == 64) {
+      return fmax(fmax(readlane_d(x, 0), readlane_d(x, 16)), fmax(readlane_d(x, 32), readlane_d(x, 48)));
+    } else if constexpr (G == 32) {
+      return fmax(x, __shfl_xor(x, 16, 64));
+    } else {
+      return x;
+    }
+  }
+  __device__ static __forceinline__ int min_i(int x) {
+    x = ::min(x, dpp_i<kXor1>(x));
+    x = ::min(x, dpp_i<kXor2>(x));
+    x = ::min(x, dpp_i<kHalfMirror>(x));
+    x = ::min(x, dpp_i<kMirror>(x));
+    if constexpr (G == 64) {
+      return ::min(::min(__builtin_amdgcn_readlane(x, 0), __builtin_amdgcn_readlane(x, 16)),
+                   ::min(__builtin_amdgcn_readlane(x, 32), __builtin_amdgcn_readlane(x, 48)));
+    } else if constexpr (G == 32) {
+      return ::min(x, __shfl_xor(x, 16, 64));
+    } else {
+      return x;
+    }
+  }
+  // group-relative ballot
+  __device__ static __forceinline__ unsigned long long ballot(bool p) {
+    const unsigned long long b = __ballot(p);
+    if constexpr (G == 64) {
+      return b;
+    } else {
+      return (b >> base()) & ((1ull << G) - 1ull);
+    }
+  }
+  __device__ static __forceinline__ bool any(bool p) { return ballot(p) != 0ull; }
+  // the group lane where p holds (p true on exactly one lane)
+  __device__ static __forceinline__ int first(bool p) {
+    return __ffsll(static_cast<long long>(ballot(p))) - 1;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// mechanism in LDS
+// ---------------------------------------------------------------------------
+struct MechLds {
+  const double *lnA, *b, *EaR, *troe, *eff_am1, *rW;
+  const uint4* rint;
+  const uint16_t *eff_sp, *sp_off, *sp_ent;
+};
+
+__device__ __forceinline__ MechLds mech_views(const unsigned char* s, const MechArgs& m) {
+  MechLds L;
+  const unsigned char* g = reinterpret_cast<const unsigned char*>(m.blob);
+  L.lnA = reinterpret_cast<const double*>(g + m.off_lnA);
+  L.b = reinterpret_cast<const double*>(g + m.off_b);
+  L.EaR = reinterpret_cast<const double*>(g + m.off_EaR);
+  L.troe = reinterpret_cast<const double*>(g + m.off_troe);
+  L.rint = reinterpret_cast<const uint4*>(s + m.off_rint);
+  L.eff_am1 = reinterpret_cast<const double*>(s + m.off_eff_am1);
+  L.eff_sp = reinterpret_cast<const uint16_t*>(s + m.off_eff_sp);
+  L.sp_off = reinterpret_cast<const uint16_t*>(s + m.off_sp_off);
+  L.sp_ent = reinterpret_cast<const uint16_t*>(s + m.off_sp_ent);
+  L.rW = reinterpret_cast<const double*>(s + m.off_rW);
+  return L;
+}
+
+__device__ __forceinline__ void stage_mech(unsigned char* smem, const MechArgs& m) {
+  uint4* d = reinterpret_cast<uint4*>(smem);
+  const int n16 = m.lds_bytes / 16;
+  for (int i = threadIdx.x; i < n16; i += blockDim.x) d[i] = m.blob[i];
+  __syncthreads();
+}
+
+// Per-cell LDS area layout (doubles): J [NN*NN] row-major, pivot-row buffer
+// P [NN+1 rounded to even], per-reaction buffers RB [5*nr] (rate of progress,
+// and with the Jacobian kf*theta, kr*theta, q0*dtheta/d[M], dq/dT), then the
+// per-species vectors C, gRT, hRT [ns each].
+struct CellArea {
+  double* J;
+  double* P;
+  double* RB;
+  double* C;
+  double* gRT;
+  double* hRT;
+};
+
+__host__ __device__ constexpr int pbuf_doubles(int nn) { return (nn + 2) & ~1; }
+__host__ __device__ constexpr int cell_doubles_c(int nn, int nr, int ns) {
+  return ((nn * nn + 1) & ~1) + pbuf_doubles(nn) + 5 * nr + 3 * ns;
+}
+
+template <int NN>
+__device__ __forceinline__ CellArea cell_area(double* base, int nr, int ns) {
+  CellArea c;
+  c.J = base;
+  c.P = base + ((NN * NN + 1) & ~1);
+  c.RB = c.P + pbuf_doubles(NN);
+  c.C = c.RB + 5 * nr;
+  c.gRT = c.C + ns;
+  c.hRT = c.gRT + ns;
+  return c;
+}
+
+// Mass-action product of one reaction side (up to 3 distinct species with
+// orders 1..3) and its partial derivative by each species, without division
+// by a concentration; branch-free (absent slots read species 0 and count as
+// order 0). sg accumulates sign * order * g/RT of the side's species.
+__device__ __forceinline__ void mass_action(const double* C, unsigned spw, unsigned ordw, int k,
+                                            double& P, double (&dP)[3], int (&sp)[3]) {
+  double pw[3], dp[3], cc[3];
+  int oo[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const bool on = j < k;
+    sp[j] = on ? (spw >> (8 * j)) & 0xff : 0;
+    oo[j] = on ? (ordw >> (4 * j)) & 0xf : 0;
+    cc[j] = C[sp[j]];
+  }
+  // keep the three loads together (one LDS round trip) rather than sunk
+  // into per-slot branches
+  asm volatile("" : "+v"(cc[0]), "+v"(cc[1]), "+v"(cc[2]));
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int o = oo[j];
+    const double c = cc[j];
+    const double c2 = c * c;
+    pw[j] = o == 0 ? 1.0 : (o == 1 ? c : (o == 2 ? c2 : c2 * c));
+    dp[j] = o == 0 ? 0.0 : (o == 1 ? 1.0 : (o == 2 ? 2.0 * c : 3.0 * c2));
+  }
+  P = pw[0] * pw[1] * pw[2];
+  dP[0] = dp[0] * pw[1] * pw[2];
+  dP[1] = pw[0] * dp[1] * pw[2];
+  dP[2] = pw[0] * pw[1] * dp[2];
+}
+
+// ---------------------------------------------------------------------------
+// one cell
+// ---------------------------------------------------------------------------
+template <int NN, int G>
+struct Cell {
+  static_assert(G >= NN, "one state component per lane");
+  using Gp = Grp<G>;
+
+  // f = dy/dt at y (this lane's component); with JAC also the analytical
+  // Jacobian df/dy, written row-major into ca.J (complete on return).
+  template <bool JAC>
+  __device__ static __forceinline__ double rhs(const MechArgs& A, const MechLds& L, const CellArea& ca,
+                                               double p, double y) {
+    const int ns = A.ns, nr = A.nr;
+    const int i = Gp::gl();                 // state component of this lane
+    const bool sp = i >= 1 && i <= ns;      // lane holds species i-1
+    const int s = sp ? i - 1 : 0;
+    const double T = Gp::bcast(y, 0);
+    const double rT = 1.0 / T;
+    const double lnT = log(T);
+    // mixture state
+    const double Ys = sp ? y : 0.0;
+    const double rWs = sp ? L.rW[s] : 0.0;
+    const double invWbar = Gp::sum(Ys * rWs);
+    const double Wbar = 1.0 / invWbar;
+    const double rho = p * Wbar / (kR * T);
+    const double Cs = rho * Ys * rWs;
+    if (sp) ca.C[s] = Cs;
+    const double Ctot = Gp::sum(Cs);
+    // species thermo (NASA-7, range by T < Tmid)
+    double cpR = 0.0, hRT = 0.0, dcpR = 0.0;
+    if (sp) {
+      const double* a = A.nasa + 16 * s;
+      if (!(T < a[7])) a += 8;
+      const double a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3], a4 = a[4], a5 = a[5], a6 = a[6];
+      cpR = fma(T, fma(T, fma(T, fma(T, a4, a3), a2), a1), a0);
+      hRT = fma(T, fma(T, fma(T, fma(T, a4 * 0.2, a3 * 0.25), a2 * (1.0 / 3.0)), a1 * 0.5), a0) + a5 * rT;
+      const double sR = fma(a0, lnT, fma(T, fma(T, fma(T, a4 * 0.25, a3 * (1.0 / 3.0)), a2 * 0.5), a1) * T) + a6;
+      if (JAC) dcpR = fma(T, fma(T, 4.0 * a4, 3.0 * a3), 2.0 * a2) * T + a1;
+      ca.gRT[s] = hRT - sR;
+      ca.hRT[s] = hRT;
+    }
+    const double cp = Gp::sum(Ys * cpR * kR * rWs);
+    double dcp = 0.0;
+    if (JAC) {
+      dcp = Gp::sum(Ys * dcpR * kR * rWs);
+      if (i < NN) {
+#pragma unroll
+        for (int j = 0; j < NN; ++j) ca.J[i * NN + j] = 0.0;
+      }
+    }
+    wsync();
+
+    // ---- reactions: one lane per reaction ----
+    const double lnRTp = log(kR * T / kPatm);
+    for (int r0 = 0; r0 < nr; r0 += G) {
+      const int rx = r0 + i;
+      if (rx >= nr) break;
+      const uint4 w = L.rint[rx];
+      const int type = (w.x >> 28) & 3;
+      const bool rev = (w.x >> 30) & 1;
+      const int nre = (w.x >> 24) & 0xf, npr = (w.y >> 24) & 0xf;
+      const int dnu = static_cast<int>((w.z >> 24) & 0x7f) - 64;
+      const double bb = L.b[rx], ear = L.EaR[rx];
+      const double lnkf = L.lnA[rx] + bb * lnT - ear * rT;
+      const double kf = exp(lnkf);
+      double Pf, Pr, sumg = 0.0, sumh = 0.0;
+      {
+        double pw[3], pr[3], cf[3], cr[3], gf[3], gr[3], hf[3], hr[3];
+        int of[3], orr[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const bool onf = j < nre, onr = j < npr;
+          const int qf = onf ? (w.x >> (8 * j)) & 0xff : 0;
+          const int qr = onr ? (w.y >> (8 * j)) & 0xff : 0;
+          of[j] = onf ? (w.z >> (4 * j)) & 0xf : 0;
+          orr[j] = onr ? (w.z >> (12 + 4 * j)) & 0xf : 0;
+          cf[j] = ca.C[qf];
+          cr[j] = ca.C[qr];
+          gf[j] = ca.gRT[qf];
+          gr[j] = ca.gRT[qr];
+          hf[j] = JAC ? ca.hRT[qf] : 0.0;
+          hr[j] = JAC ? ca.hRT[qr] : 0.0;
+        }
+        // one LDS round trip for all species data of the reaction
+        asm volatile("" : "+v"(cf[0]), "+v"(cf[1]), "+v"(cf[2]), "+v"(cr[0]), "+v"(cr[1]), "+v"(cr[2]));
+        asm volatile("" : "+v"(gf[0]), "+v"(gf[1]), "+v"(gf[2]), "+v"(gr[0]), "+v"(gr[1]), "+v"(gr[2]));
+        if (JAC) asm volatile("" : "+v"(hf[0]), "+v"(hf[1]), "+v"(hf[2]), "+v"(hr[0]), "+v"(hr[1]), "+v"(hr[2]));
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const double cf2 = cf[j] * cf[j], cr2 = cr[j] * cr[j];
+          pw[j] = of[j] == 0 ? 1.0 : (of[j] == 1 ? cf[j] : (of[j] == 2 ? cf2 : cf2 * cf[j]));
+          pr[j] = orr[j] == 0 ? 1.0 : (orr[j] == 1 ? cr[j] : (orr[j] == 2 ? cr2 : cr2 * cr[j]));
+          sumg = sumg - of[j] * gf[j];
+          sumg = sumg + orr[j] * gr[j];
+          if (JAC) {
+            sumh = sumh - of[j] * hf[j];
+            sumh = sumh + orr[j] * hr[j];
+          }
+        }
+        Pf = pw[0] * pw[1] * pw[2];
+        Pr = pr[0] * pr[1] * pr[2];
+      }
+      // kr = kf / Kc with Kc = exp(-sum nu g/RT) (p_atm/RT)^(sum nu)
+      const double kr = rev ? exp(lnkf + sumg + dnu * lnRTp) : 0.0;
+      const double q0 = kf * Pf - kr * Pr;
+      double theta = 1.0, beta = 0.0, dthdT = 0.0;
+      const double dlnkf = (bb + ear * rT) * rT;
+      if (type >= 1) {
+        double M = Ctot;
+        const int eoff = w.w & 0xffff, neff = (w.w >> 16) & 0xff;
+        for (int e = 0; e < neff; ++e) M = M + L.eff_am1[eoff + e] * ca.C[L.eff_sp[eoff + e]];
+        if (type == 1) {
+          theta = M;
+          beta = 1.0;
+        } else {
+          const double* tr = L.troe + 8 * ((w.w >> 24) & 0xff);
+          const double k0 = exp(tr[0] + tr[1] * lnT - tr[2] * rT);
+          const double dlnk0 = (tr[1] + tr[2] * rT) * rT;
+          double Prd = k0 * M / kf;
+          if (Prd < 1e-300) Prd = 1e-300;
+          const double ta = tr[3];
+          const double e3 = exp(-T * tr[4]), e1 = exp(-T * tr[5]);
+          double Fc = (1.0 - ta) * e3 + ta * e1;
+          double dFc = -(1.0 - ta) * tr[4] * e3 - ta * tr[5] * e1;
+          if (tr[7] != 0.0) {
+            const double e2 = exp(-tr[6] * rT);
+            Fc = Fc + e2;
+            dFc = dFc + tr[6] * rT * rT * e2;
+          }
+          if (Fc < 1e-300) Fc = 1e-300;
+          const double Lc = log10(Fc);
+          const double c = -0.4 - 0.67 * Lc;
+          const double N = 0.75 - 1.27 * Lc;
+          const double X = log10(Prd) + c;
+          const double den = N - 0.14 * X;
+          const double f1 = X / den;
+          const double opf = 1.0 + f1 * f1;
+          const double lgF = Lc / opf;
+          const double F = exp(lgF * kLn10);
+          const double lind = Prd / (1.0 + Prd);
+          theta = lind * F;
+          if (JAC) {
+            const double dlogF_dX = -Lc * 2.0 * f1 / (opf * opf) * (N / (den * den));
+            const double dlogF_dPr = dlogF_dX / (Prd * kLn10);
+            const double dPhi = F / ((1.0 + Prd) * (1.0 + Prd)) + lind * F * kLn10 * dlogF_dPr;
+            beta = dPhi * k0 / kf;
+            const double dPr_dT = Prd * (dlnk0 - dlnkf);
+            const double dL_dT = dFc / (Fc * kLn10);
+            const double df1_dL = (-0.67 * den - X * (-1.27 + 0.14 * 0.67)) / (den * den);
+            const double dlogF_dL = 1.0 / opf - Lc * 2.0 * f1 * df1_dL / (opf * opf);
+            dthdT = dPhi * dPr_dT + lind * (F * kLn10 * dlogF_dL * dL_dT);
+          }
+        }
+      }
+      ca.RB[rx] = theta * q0;
+      if (JAC) {
+        const double dlnkr = rev ? dlnkf - (sumh * rT - dnu * rT) : 0.0;
+        ca.RB[nr + rx] = kf * theta;
+        ca.RB[2 * nr + rx] = kr * theta;
+        ca.RB[3 * nr + rx] = q0 * beta;
+        ca.RB[4 * nr + rx] = theta * (kf * dlnkf * Pf - kr * dlnkr * Pr) + q0 * dthdT;
+      }
+    }
+    wsync();
+
+    // ---- species: production rates (and sparse Jacobian rows d omega/dC) ----
+    // The Jacobian row is accumulated with LDS adds that return nothing (the
+    // lane owns its row, and one wave's LDS operations execute in order, so
+    // the sum order is the program order); the next entry's records are
+    // fetched before the current one is processed.
+    double om = 0.0, wT = 0.0, td = 0.0;
+    if (sp) {
+      const int e0 = L.sp_off[s], e1 = L.sp_off[s + 1];
+      double* Jrow = ca.J + i * NN + 1;
+      if (!JAC) {
+#pragma unroll 4
+        for (int e = e0; e < e1; ++e) {
+          const unsigned ent = L.sp_ent[e];
+          const double nu = static_cast<double>(static_cast<int>(ent >> 12) - 8);
+          om = om + nu * ca.RB[ent & 0xfff];
+        }
+      } else {
+        unsigned ent = e0 < e1 ? L.sp_ent[e0] : 0u;
+        uint4 w = L.rint[ent & 0xfff];
+        for (int e = e0; e < e1; ++e) {
+          const int rx = ent & 0xfff;
+          const double nu = static_cast<double>(static_cast<int>(ent >> 12) - 8);
+          const uint4 wc = w;
+          // prefetch the next entry
+          const unsigned ent_n = e + 1 < e1 ? L.sp_ent[e + 1] : ent;
+          double qr = ca.RB[rx], kfT = ca.RB[nr + rx], krT = ca.RB[2 * nr + rx];
+          double q0b = ca.RB[3 * nr + rx], dqdT = ca.RB[4 * nr + rx];
+          asm volatile("" : "+v"(qr), "+v"(kfT), "+v"(krT), "+v"(q0b), "+v"(dqdT));
+          const int nre = (wc.x >> 24) & 0xf, npr = (wc.y >> 24) & 0xf;
+          double Pf, Pr, dPf[3], dPr[3];
+          int sf[3], sr[3];
+          mass_action(ca.C, wc.x, wc.z, nre, Pf, dPf, sf);
+          mass_action(ca.C, wc.y, wc.z >> 12, npr, Pr, dPr, sr);
+          w = L.rint[ent_n & 0xfff];
+          ent = ent_n;
+          om = om + nu * qr;
+          wT = wT + nu * dqdT;
+          const double af = nu * kfT, ar = nu * krT;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) lds_add(j < nre ? &Jrow[sf[j]] : ca.P, af * dPf[j]);
+#pragma unroll
+          for (int j = 0; j < 3; ++j) lds_add(j < npr ? &Jrow[sr[j]] : ca.P, -(ar * dPr[j]));
+          const int type = (wc.x >> 28) & 3;
+          if (type >= 1) {
+            const double ab = nu * q0b;
+            td = td + ab;
+            const int eoff = wc.w & 0xffff, neff = (wc.w >> 16) & 0xff;
+            for (int q = 0; q < neff; ++q) lds_add(&Jrow[L.eff_sp[eoff + q]], ab * L.eff_am1[eoff + q]);
+          }
+        }
+      }
+    }
+    const double fY = sp ? A.W[s] * om / rho : 0.0;
+    const double Q = Gp::sum(hRT * kR * T * om);
+    const double rcp = rho * cp;
+    const double fT = -Q / rcp;
+    const double f = (i == 0) ? fT : fY;
+    if (!JAC) return f;
+
+    // ---- Jacobian: chain rule from d(omega)/dC, d(omega)/dT to y = (T, Y) ----
+    wsync();
+    double sv = 0.0;
+    if (sp) {
+      const double* Jrow = ca.J + i * NN + 1;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+      for (int k = 0; k < NN - 1; k += 4) {
+        if (k < ns) a0 = fma(Jrow[k], ca.C[k], a0);
+        if (k + 1 < ns && k + 1 < NN - 1) a1 = fma(Jrow[k + 1], ca.C[k + 1], a1);
+        if (k + 2 < ns && k + 2 < NN - 1) a2 = fma(Jrow[k + 2], ca.C[k + 2], a2);
+        if (k + 3 < ns && k + 3 < NN - 1) a3 = fma(Jrow[k + 3], ca.C[k + 3], a3);
+      }
+      sv = ((a0 + a1) + (a2 + a3)) + td * Ctot;
+    }
+    const double HS = Gp::sum(hRT * sv);
+    const double HT = Gp::sum(hRT * td);
+    const double dQdT = Gp::sum(sp ? cpR * kR * om + hRT * kR * T * (wT - sv / T) : 0.0);
+    // T-row entry of column i (species i-1): lane i sums column i of D
+    double JT = 0.0;
+    if (sp) {
+      double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+#pragma unroll
+      for (int q = 0; q < NN - 1; q += 4) {
+        if (q < ns) c0 = fma(ca.hRT[q], ca.J[(1 + q) * NN + i], c0);
+        if (q + 1 < ns && q + 1 < NN - 1) c1 = fma(ca.hRT[q + 1], ca.J[(2 + q) * NN + i], c1);
+        if (q + 2 < ns && q + 2 < NN - 1) c2 = fma(ca.hRT[q + 2], ca.J[(3 + q) * NN + i], c2);
+        if (q + 3 < ns && q + 3 < NN - 1) c3 = fma(ca.hRT[q + 3], ca.J[(4 + q) * NN + i], c3);
+      }
+      const double cs = (c0 + c1) + (c2 + c3);
+      const double dQdY = kR * T * ((rho * rWs) * (cs + HT) - (Wbar * rWs) * HS);
+      const double drcp = rho * cpR * kR * rWs - rcp * Wbar * rWs;
+      JT = -(dQdY + fT * drcp) / rcp;
+    }
+    wsync();
+    if (sp) {
+      double* Jrow = ca.J + i * NN;
+      const double Wi_rho = A.W[s] / rho;
+#pragma unroll
+      for (int k = 0; k < NN - 1; ++k) {
+        if (k < ns) {
+          const double rWk = L.rW[k];
+          const double D = Jrow[1 + k] + td;
+          const double dw = (rho * rWk) * D - (Wbar * rWk) * sv;
+          Jrow[1 + k] = Wi_rho * dw + fY * Wbar * rWk;
+        }
+      }
+      Jrow[0] = Wi_rho * (wT - sv / T) + fY / T;
+      ca.J[i] = JT;
+    } else if (i == 0) {
+      const double drcp = -rcp / T + rho * dcp;
+      ca.J[0] = -(dQdT + fT * drcp) / rcp;
+    }
+    wsync();
+    return f;
+  }
+
+  // -------------------------------------------------------------------------
+  // LU with partial pivoting of the rows in registers (row = lane). Rows are
+  // not moved during the elimination: pos tracks each row's LAPACK position,
+  // so the pivot of column k is the largest |a| among rows at positions >= k,
+  // ties to the lowest position, exactly as a row-swapping getrf. The pivot
+  // row reaches the other lanes through the LDS buffer P. At the end every
+  // row is sent to the lane of its position (one ds_permute per dword), so on
+  // return lane k holds row k of the packed factors (L left of the diagonal,
+  // unit diagonal implied; U from the diagonal on) and rdiag = 1/U_kk; pos
+  // keeps the position this lane's original row went to (used to permute
+  // right-hand sides). Returns the first singular column + 1.
+  // -------------------------------------------------------------------------
+  __device__ static __forceinline__ int lu(double (&M)[NN], int& pos, double& rdiag, double* P, int* pivk) {
+    int info = 0;
+    const int i = Gp::gl();
+    pos = i < NN ? i : kBig;
+    rdiag = 0.0;
+#pragma unroll
+    for (int k = 0; k < NN; ++k) {
+      const double a = M[k];
+      const bool cand = pos >= k && pos < NN;
+      const double key = cand ? fabs(a) : -1.0;
+      const double amax = Gp::max(key);
+      const bool tie = key == amax;
+      const unsigned long long bal = Gp::ballot(tie);
+      int owner;
+      if (__popcll(bal) == 1) {
+        owner = __ffsll(static_cast<long long>(bal)) - 1;
+      } else {
+        const int pmin = Gp::min_i(tie ? pos : kBig);
+        owner = Gp::first(tie && pos == pmin);
+      }
+      const int ppos = Gp::bcast_i(pos, owner);
+      const bool is_owner = i == owner;
+      if (is_owner) {
+        pos = k;
+      } else if (pos == k) {
+        pos = ppos;
+      }
+      if (pivk) pivk[k] = ppos;
+      const double akk = Gp::bcast(a, owner);
+      double rp;
+      if (amax == 0.0) {
+        if (info == 0) info = k + 1;
+        rp = 0.0;
+      } else {
+        rp = 1.0 / akk;
+      }
+      if (is_owner) rdiag = rp;
+      const bool below = pos > k && pos < NN;
+      const double l = below ? a * rp : 0.0;
+      if (below) M[k] = l;
+#pragma unroll
+      for (int j = k + 1; j < NN; ++j) M[j] = fma(-l, Gp::bcast(M[j], owner), M[j]);
+    }
+    // rows to the lanes of their positions
+    const int dst = 4 * (Gp::base() + (pos < NN ? pos : i));
+#pragma unroll
+    for (int j = 0; j < NN; ++j) M[j] = permute_d(M[j], dst);
+    rdiag = permute_d(rdiag, dst);
+    return info;
+  }
+
+  // lane gl() receives the value of the lane whose byte address it is sent to
+  __device__ static __forceinline__ double permute_d(double v, int dst_addr) {
+    const int lo = __builtin_amdgcn_ds_permute(dst_addr, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_permute(dst_addr, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+  }
+
+  // Solve M x = b with the factors of lu(); b is this lane's equation (row
+  // gl() of M), the return value is solution component gl(). The right-hand
+  // side is first sent to position order; both substitutions then broadcast
+  // from fixed lanes.
+  __device__ static __forceinline__ double solve(const double (&M)[NN], int pos, double rdiag, double b) {
+    const int i = Gp::gl();
+    b = permute_d(b, 4 * (Gp::base() + (pos < NN ? pos : i)));
+#pragma unroll
+    for (int j = 0; j < NN - 1; ++j) {
+      const double z = Gp::bcast(b, j);
+      if (i > j) b = fma(-M[j], z, b);
+    }
+#pragma unroll
+    for (int j = NN - 1; j > 0; --j) {
+      const double z = Gp::bcast(b * rdiag, j);
+      if (i < j) b = fma(-M[j], z, b);
+    }
+    return b * rdiag;
+  }
+
+  // -------------------------------------------------------------------------
+  // adaptive Rodas3 over [0, dt] for one cell (y: this lane's component)
+  // -------------------------------------------------------------------------
+  __device__ static __forceinline__ void integrate(const MechArgs& A, const MechLds& L, const CellArea& ca,
+                                                   const OptsDev& o, double p, double dt, double& y,
+                                                   double& hio, int& nacc_o, int& nrej_o, int& status_o) {
+    const int ns = A.ns;
+    const int n = ns + 1;
+    const int i = Gp::gl();
+    const bool valid = i <= ns;
+    double M[NN];
+    int pos;
+    double rdiag;
+    int status = 0;
+    if (Gp::any((valid && !isfinite(y)) || !isfinite(p))) status = 3;
+    double h = hio > 0.0 ? hio : dt;
+    double hnext = h, t = 0.0;
+    int nacc = 0, nrej = 0, att = 0, consec = 0;
+    bool need = true;
+    double f0 = 0.0;
+    while (status == 0 && t < dt) {
+      if (att >= o.max_steps) {
+        status = 1;
+        break;
+      }
+      if (need) {
+        f0 = rhs<true>(A, L, ca, p, y);
+        need = false;
+      }
+      const double rem = dt - t;
+      double hc = h;
+      bool clipped = false;
+      if (hc >= rem) {
+        hc = rem;
+        clipped = true;
+      }
+      if (hc < kHMin) {
+        status = 2;
+        break;
+      }
+      const double g = 1.0 / (kGamma * hc);
+      if (i < NN) {
+#pragma unroll
+        for (int j = 0; j < NN; ++j) M[j] = (i == j ? g : 0.0) - ca.J[i * NN + j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < NN; ++j) M[j] = 0.0;
+      }
+      const int info = lu(M, pos, rdiag, ca.P, nullptr);
+      ++att;
+      if (info) {
+        status = 4;
+        break;
+      }
+      // stages: one right-hand side and one solve call site for all four
+      double u1 = 0.0, u2 = 0.0, u3 = 0.0, u4 = 0.0;
+#pragma nounroll
+      for (int st = 0; st < 4; ++st) {
+        double v;
+        if (st == 0) {
+          v = f0;
+        } else if (st == 1) {
+          v = f0 + (kC21 / hc) * u1;
+        } else {
+          const bool s3 = st == 2;
+          double ys = y + (s3 ? kA31 : kA41) * u1;
+          ys = ys + 0.0 * u2;
+          if (!s3) ys = ys + kA43 * u3;
+          const double fs = rhs<false>(A, L, ca, p, ys);
+          v = fs + ((s3 ? kC31 : kC41) / hc) * u1;
+          v = v + ((s3 ? kC32 : kC42) / hc) * u2;
+          if (!s3) v = v + (kC43 / hc) * u3;
+        }
+        const double x = solve(M, pos, rdiag, v);
+        if (st == 0) u1 = x;
+        else if (st == 1) u2 = x;
+        else if (st == 2) u3 = x;
+        else u4 = x;
+      }
+      // new solution and error estimate
+      double yn = y + 2.0 * u1;
+      yn = yn + 0.0 * u2;
+      yn = yn + 1.0 * u3;
+      yn = yn + 1.0 * u4;
+      const double sc = o.atol + o.rtol * fmax(fabs(y), fabs(yn));
+      const double q = u4 / sc;
+      const double acc = Gp::sum(valid ? q * q : 0.0);
+      double err = sqrt(acc / n);
+      double hnew;
+      if (Gp::any(valid && !isfinite(yn)) || !isfinite(err)) {
+        err = INFINITY;
+        hnew = hc * kFacRej;
+      } else {
+        double fac = kFacSafe / cbrt(fmax(err, 1e-10));
+        fac = fmin(kFacMax, fmax(kFacMin, fac));
+        hnew = hc * fac;
+      }
+      if (err <= 1.0) {
+        if (consec > 0) hnew = fmin(hnew, hc);
+        const double Tn = Gp::bcast(yn, 0);
+        if (!(Tn >= kTMin && Tn <= kTMax)) {
+          status = 5;
+          break;
+        }
+        y = yn;
+        ++nacc;
+        t = clipped ? dt : t + hc;
+        hnext = clipped ? fmax(hnew, h) : hnew;
+        h = hnew;
+        consec = 0;
+        need = true;
+      } else {
+        ++nrej;
+        ++consec;
+        if (consec >= 2) hnew = hc * kFacRej;
+        h = hnew;
+      }
+    }
+    if (status != 0) hnext = h;
+    hio = hnext;
+    nacc_o = nacc;
+    nrej_o = nrej;
+    status_o = status;
+  }
+};
+
+// features for the learned cost model: (T-1500)/700, ln(p/1e5),
+// mean log10 max(Y, 1e-30) / 10, log10(dt/1e-6)
+template <int G>
+__device__ __forceinline__ void cell_features(int ns, double y, double p, double dt, float (&ft)[4]) {
+  const int i = Grp<G>::gl();
+  const double lv = (i >= 1 && i <= ns) ? log10(fmax(y, 1e-30)) : 0.0;
+  const double ell = Grp<G>::sum(lv) / ns;
+  const double T = Grp<G>::bcast(y, 0);
+  ft[0] = static_cast<float>((T - 1500.0) / 700.0);
+  ft[1] = static_cast<float>(log(p / 1e5));
+  ft[2] = static_cast<float>(ell / 10.0);
+  ft[3] = static_cast<float>(log10(dt / 1e-6));
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+template <int NN, int G>
+__device__ __forceinline__ void run_cell(const IntegrateArgs& a, const MechLds& L, const CellArea& ca,
+                                         long long cell) {
+  using C = Cell<NN, G>;
+  const int ns = a.m.ns;
+  const int w2 = ns + 2;
+  const int i = Grp<G>::gl();
+  const double* pin = a.phi_in + cell * w2;
+  const double p = pin[1];
+  double y = i == 0 ? pin[0] : (i <= ns ? pin[1 + i] : 0.0);
+  float ft[4];
+  if (a.log.cap > 0) cell_features<G>(ns, y, p, a.dt, ft);
+  double h = a.h_io ? a.h_io[cell] : 0.0;
+  int nacc, nrej, st;
+  C::integrate(a.m, L, ca, a.o, p, a.dt, y, h, nacc, nrej, st);
+  double* pout = a.phi_out + cell * w2;
+  if (i == 0) {
+    pout[0] = y;
+    pout[1] = p;
+  } else if (i <= ns) {
+    pout[1 + i] = y;
+  }
+  if (i == 0) {
+    if (a.h_io) a.h_io[cell] = h;
+    if (a.accumulate) {
+      if (a.n_acc) a.n_acc[cell] += nacc;
+      if (a.n_rej) a.n_rej[cell] += nrej;
+      if (a.status && a.status[cell] == 0) a.status[cell] = static_cast<signed char>(st);
+    } else {
+      if (a.n_acc) a.n_acc[cell] = nacc;
+      if (a.n_rej) a.n_rej[cell] = nrej;
+      if (a.status) a.status[cell] = static_cast<signed char>(st);
+    }
+    if (a.log.cap > 0) {
+      const unsigned long long k = atomicAdd(a.log.head, 1ull) % static_cast<unsigned long long>(a.log.cap);
+      a.log.feats[4 * k + 0] = ft[0];
+      a.log.feats[4 * k + 1] = ft[1];
+      a.log.feats[4 * k + 2] = ft[2];
+      a.log.feats[4 * k + 3] = ft[3];
+      a.log.target[k] = logf(static_cast<float>(nacc + nrej > 0 ? nacc + nrej : 1));
+    }
+  }
+}
+
+// Large state sizes run one wave per SIMD (the per-cell LDS area allows no
+// more), so let the register allocator use the whole 512-entry budget.
+template <int NN>
+constexpr int max_waves_per_eu() { return NN >= 32 ? 1 : 2; }
+
+template <int NN, int G, bool PERSIST>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, max_waves_per_eu<NN>())))
+k_integrate(IntegrateArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  stage_mech(smem, a.m);
+  const MechLds L = mech_views(smem, a.m);
+  constexpr int CPW = 64 / G;
+  const int wave = threadIdx.x / 64;
+  const int grp = (threadIdx.x % 64) / G;
+  double* base = reinterpret_cast<double*>(smem + a.m.lds_bytes) +
+                 static_cast<long long>(wave * CPW + grp) * a.cell_doubles;
+  const CellArea ca = cell_area<NN>(base, a.m.nr, a.m.ns);
+  if (!PERSIST) {
+    const long long cell = (static_cast<long long>(blockIdx.x) * a.wpb + wave) * CPW + grp;
+    if (cell < a.n) run_cell<NN, G>(a, L, ca, cell);
+  } else {
+    for (;;) {
+      unsigned long long idx = 0;
+      if (Grp<G>::gl() == 0) idx = atomicAdd(a.head, static_cast<unsigned long long>(a.chunk));
+      idx = static_cast<unsigned long long>(__shfl(static_cast<long long>(idx), Grp<G>::base(), 64));
+      if (idx >= static_cast<unsigned long long>(a.n)) break;
+      const long long end = min(static_cast<long long>(idx) + a.chunk, a.n);
+      for (long long q = static_cast<long long>(idx); q < end; ++q) {
+        const long long cell = a.perm ? static_cast<long long>(a.perm[q]) : q;
+        run_cell<NN, G>(a, L, ca, cell);
+      }
+    }
+  }
+}
+
+template <int NN, int G>
+__global__ void __launch_bounds__(256) k_eval(EvalArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  stage_mech(smem, a.m);
+  const MechLds L = mech_views(smem, a.m);
+  using C = Cell<NN, G>;
+  constexpr int CPW = 64 / G;
+  const int wave = threadIdx.x / 64;
+  const int grp = (threadIdx.x % 64) / G;
+  double* base = reinterpret_cast<double*>(smem + a.m.lds_bytes) +
+                 static_cast<long long>(wave * CPW + grp) * a.cell_doubles;
+  const CellArea ca = cell_area<NN>(base, a.m.nr, a.m.ns);
+  const long long cell = (static_cast<long long>(blockIdx.x) * a.wpb + wave) * CPW + grp;
+  if (cell >= a.n) return;
+  const int ns = a.m.ns, n = ns + 1;
+  const int i = Grp<G>::gl();
+  const double* pin = a.phi + cell * (ns + 2);
+  const double p = pin[1];
+  const double y = i == 0 ? pin[0] : (i <= ns ? pin[1 + i] : 0.0);
+  const double f = a.J ? C::template rhs<true>(a.m, L, ca, p, y) : C::template rhs<false>(a.m, L, ca, p, y);
+  if (i < n) {
+    a.f[cell * n + i] = f;
+    if (a.J)
+      for (int j = 0; j < n; ++j) a.J[(cell * n + i) * n + j] = ca.J[i * NN + j];
+  }
+}
+
+template <int NN, int G>
+__global__ void __launch_bounds__(256) k_lu(LuArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using C = Cell<NN, G>;
+  constexpr int CPW = 64 / G;
+  const int wave = threadIdx.x / 64;
+  const int grp = (threadIdx.x % 64) / G;
+  double* P = reinterpret_cast<double*>(smem) + (wave * CPW + grp) * pbuf_doubles(NN);
+  const long long m = (static_cast<long long>(blockIdx.x) * a.wpb + wave) * CPW + grp;
+  if (m >= a.batch) return;
+  const int n = a.n;
+  const int i = Grp<G>::gl();
+  double M[NN];
+#pragma unroll
+  for (int j = 0; j < NN; ++j)
+    M[j] = (i < n && j < n) ? a.A[(m * n + i) * n + j] : (i == j && i < NN ? 1.0 : 0.0);
+  int pivk[NN];
+  int pos;
+  double rdiag;
+  const int info = C::lu(M, pos, rdiag, P, pivk);
+  if (i < n) {
+#pragma unroll
+    for (int j = 0; j < NN; ++j)
+      if (j < n) a.A[(m * n + i) * n + j] = M[j];
+  }
+  if (i == 0) {
+#pragma unroll
+    for (int k = 0; k < NN; ++k)
+      if (k < n) a.piv[m * n + k] = pivk[k];
+    a.info[m] = info;
+  }
+  if (a.b) {
+    const double b = i < n ? a.b[m * n + i] : 0.0;
+    const double x = C::solve(M, pos, rdiag, b);
+    if (i < n) a.b[m * n + i] = x;
+  }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v) { *p = v; }
+
+__global__ void k_copy_f64(double* dst, const double* src, long long n) {
+  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    dst[i] = src[i];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+#define CHEM_VARIANTS(X) \
+  X(10, 16)              \
+  X(10, 64)              \
+  X(16, 16)              \
+  X(32, 32)              \
+  X(55, 64)              \
+  X(64, 64)
+
+int variants_for(int n, Variant* out, int max_out) {
+  // exact sizes first, then the smallest padded size
+  static const Variant all[] = {
+#define V(a, b) {a, b},
+      CHEM_VARIANTS(V)
+#undef V
+  };
+  int cnt = 0, best_nn = 1 << 30;
+  for (const Variant& v : all)
+    if (v.nn >= n && v.nn < best_nn) best_nn = v.nn;
+  for (const Variant& v : all)
+    if (v.nn == best_nn && cnt < max_out) out[cnt++] = v;
+  return cnt;
+}
+
+int cell_doubles(int nn, int nr, int ns) { return cell_doubles_c(nn, nr, ns); }
+
+template <int NN, int G, bool P>
+static void* integrate_fn() {
+  return reinterpret_cast<void*>(&k_integrate<NN, G, P>);
+}
+
+static void* find_integrate(const Variant& v, bool persistent) {
+#define V(a, b)                                                                                        \
+  if (v.nn == a && v.g == b) return persistent ? integrate_fn<a, b, true>() : integrate_fn<a, b, false>();
+  CHEM_VARIANTS(V)
+#undef V
+  return nullptr;
+}
+
+hipError_t launch_integrate(const Variant& v, bool persistent, int grid, const IntegrateArgs& a,
+                            size_t lds_bytes, hipStream_t st) {
+  void* fn = find_integrate(v, persistent);
+  if (!fn) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
+  if (e != hipSuccess) return e;
+  dim3 block(64 * a.wpb);
+  IntegrateArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchKernel(fn, dim3(grid), block, args, lds_bytes, st);
+}
+
+int integrate_blocks_per_cu(const Variant& v, bool persistent, int wpb, size_t lds_bytes) {
+  void* fn = find_integrate(v, persistent);
+  if (!fn) return 0;
+  hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * wpb, lds_bytes) != hipSuccess) return 0;
+  return nb;
+}
+
+hipError_t launch_eval(const Variant& v, int grid, const EvalArgs& a, size_t lds_bytes, hipStream_t st) {
+  void* fn = nullptr;
+#define V(x, y) \
+  if (v.nn == x && v.g == y) fn = reinterpret_cast<void*>(&k_eval<x, y>);
+  CHEM_VARIANTS(V)
+#undef V
+  if (!fn) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
+  if (e != hipSuccess) return e;
+  EvalArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchKernel(fn, dim3(grid), dim3(64 * a.wpb), args, lds_bytes, st);
+}
+
+hipError_t launch_lu(const Variant& v, int grid, const LuArgs& a, hipStream_t st) {
+  void* fn = nullptr;
+#define V(x, y) \
+  if (v.nn == x && v.g == y) fn = reinterpret_cast<void*>(&k_lu<x, y>);
+  CHEM_VARIANTS(V)
+#undef V
+  if (!fn) return hipErrorInvalidValue;
+  LuArgs copy = a;
+  void* args[] = {&copy};
+  const size_t lds = sizeof(double) * pbuf_doubles(v.nn) * a.wpb * (64 / v.g);
+  return hipLaunchKernel(fn, dim3(grid), dim3(64 * a.wpb), args, lds, st);
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, st, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(double* dst, const double* src, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_copy_f64, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, dst, src, n);
+  return hipGetLastError();
+}
+
+}  // namespace chemk
