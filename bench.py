@@ -77,10 +77,12 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedules", default="plain,persistent")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(cells are independent; multi-GPU sharding is described in DESIGN.md)" % args.gpus,
+              "(cells are independent: a multi-GPU run would give each GPU its own share of the cells)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
@@ -94,6 +96,15 @@ def main():
     M = chem.Mechanism(path)
     S = chem.Solver(M, chem.default_opts(), device=0)
     x = torch.from_numpy(phi).to("cuda:0")
+    if args.copy_calibration > 0:
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("bench: copy calibration, %d bytes read and %d bytes written" % (nb, nb), file=sys.stderr, flush=True)
+        del src, dst
     n_cells = phi.shape[0]
     n = mech.n_species + 1
     work = M.work()
