@@ -1,15 +1,24 @@
 """Throughput of the per-cell stiff chemistry integration on one MI355X.
 
-One step = one chemistry step of every cell of the workload (all cells
-integrated over dt from the same seeded synthetic input batch, resident in
-HBM). Prints one JSON line. The metric is cells integrated per second per
-chemistry step on the 54-species FP64 workload; the roofline object refers
-to the integration kernel, whose algorithmic flops per launch are counted
-from the mechanism's structure and each cell's accepted/rejected step counts.
+One step = one chemistry step of every cell of the workload: all cells
+integrated over dt from the same seeded synthetic batch, resident in HBM.
+The headline schedule is the persistent kernel with its work queue ordered
+by the learned cost model (features, MLP inference and binning are inside
+the timed step; training on logged samples of other seeds is not). Plain
+(one launch, static cell-to-wave mapping), persistent in index order, and
+persistent with bins of the true cost are timed beside it.
+
+Prints one JSON line. The roofline object describes the headline's
+integration kernel: algorithmic FP64 flops counted from the mechanism's
+structure and every cell's accepted/rejected step counts, over the kernel's
+own duration measured with HIP events recorded around its launches on the
+stream it runs on.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import tempfile
 import time
@@ -18,8 +27,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "cells integrated/s per chemistry step (54-sp FP64), binned persistent vs plain"
-FP64_VECTOR_PEAK = 78.6e12        # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+FP64_VECTOR_PEAK = 78.6e12        # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 HBM_PEAK = 8.0e12
+TRAIN_SEEDS = {"spray54_262144": list(range(1040, 1048)),
+               "spray54_heavytail_1048576": list(range(1040, 1042)),
+               "tiny9_1024": [1010, 1011]}
 
 
 def flops_per_launch(work, n, n_acc, n_rej):
@@ -35,37 +47,98 @@ def flops_per_launch(work, n, n_acc, n_rej):
     return starts * f_start + att * f_att
 
 
-def time_schedule(S, chem, torch, x, dt, steps, warmup, **opts):
+def measured_traffic(kernel_src):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "k_integrate_spray54_262144_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"sha256 prefix ([0-9a-f]+)", text)
+    t = re.search(r"total ([0-9.]+) MB\.", text)
+    if not m or not t:
+        return None
+    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    return float(t.group(1)) * 1e6 if h.startswith(m.group(1)) else None
+
+
+def time_schedule(S, chem, torch, x, dt, steps, warmup, chain, **opts):
+    """(last result, wall s, per-step event ms, per-launch kernel ms)."""
     S.set_opts(chem.default_opts(**opts))
     out = torch.empty_like(x)
+
+    def one():
+        if chain > 1:
+            return S.integrate_steps(x, dt, chain, h_io=False, out=out)
+        return S.integrate(x, dt, h_io=False, out=out)
+
     for _ in range(warmup):
-        r = S.integrate(x, dt, h_io=False, out=out)
+        r = one()
     torch.cuda.synchronize()
+    S.kernel_timing(True)
     st = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         ev[k][0].record(st)
-        r = S.integrate(x, dt, h_io=False, out=out)
+        r = one()
         ev[k][1].record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    kms = S.kernel_times()
+    S.kernel_timing(False)
     ms = [a.elapsed_time(b) for a, b in ev]
-    return r, wall, ms
+    return r, wall, ms, kms
 
 
-def cpu_baseline(path, phi, dt, n_sample, seed):
+def train_model(S, chem, torch, synth, wl, mech, seeds, log):
+    """Log (features, ln substeps) of every cell of other seeds' states in
+    one persistent step each, then train the predictor on all of them."""
+    t0 = time.perf_counter()
+    feats, targ = [], []
+    S.set_opts(chem.default_opts(schedule=chem.PERSISTENT))
+    for sd in seeds:
+        phi = synth.generate_states(mech, wl.n_cells, wl.pressure, wl.recipe, sd)
+        x = torch.from_numpy(phi).to("cuda:0")
+        S.log_enable(x.shape[0])
+        S.integrate(x, wl.dt, h_io=False)
+        f, t = S.log_fetch(x.shape[0])
+        feats.append(f.clone())
+        targ.append(t.clone())
+        del x
+        log("logged training seed %d" % sd)
+    S.log_enable(0)
+    F = torch.cat(feats).contiguous()
+    T = torch.cat(targ).contiguous()
+    t1 = time.perf_counter()
+    S.model_train(F, T, chem.default_train_opts())
+    torch.cuda.synchronize()
+    loss, _ = S.model_grad(F, T)
+    t2 = time.perf_counter()
+    return {"samples": int(F.shape[0]), "seeds": seeds, "log_s": t1 - t0, "train_s": t2 - t1,
+            "mse_ln_substeps": float(loss.cpu()[0]), "target_var": float(T.var().cpu())}
+
+
+def cpu_baseline(path, phi, dt, budget_s, seed):
+    """The oracle on a seeded uniform sample of the workload's cells, in
+    chunks, until about budget_s of wall time has passed."""
+    import numpy as np
+
     from oracle import oracle as O
-    from paper_2112_05834_amd import synth
-    idx = synth.sample_indices(phi.shape[0], n_sample, seed)
+    idx = np.random.Generator(np.random.PCG64(seed)).permutation(phi.shape[0])[:65536]
     cores = os.cpu_count() or 1
     M = O.Mech(path)
+    done, chunk = 0, 4 * cores
     t0 = time.perf_counter()
-    out, h, na, nr, st = M.integrate(phi[idx], dt, n_threads=cores)
+    while done < len(idx) and time.perf_counter() - t0 < budget_s:
+        sel = idx[done:done + chunk]
+        M.integrate(phi[sel], dt, n_threads=cores)
+        done += len(sel)
     wall = time.perf_counter() - t0
-    return {"value": len(idx) / wall, "unit": "cells/s", "cores": cores, "kind": "oracle",
-            "sample": "%d seeded uniformly sampled cells of the same workload (seed %d), "
-                      "all host threads, %.1f s wall" % (len(idx), seed, wall)}
+    return {"value": done / wall, "unit": "cells/s", "cores": cores, "kind": "oracle",
+            "sample": "%d cells drawn uniformly at random (seed %d) from the workload, in chunks of %d until "
+                      "%.0f s had passed; %d host threads, %.1f s wall" % (done, seed, chunk, budget_s, cores, wall)}
 
 
 def main():
@@ -74,9 +147,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="spray54_262144")
-    ap.add_argument("--cpu-sample", type=int, default=384)
+    ap.add_argument("--chain", type=int, default=1, help="chemistry steps per graph launch (chained in a HIP graph)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--schedules", default="plain,persistent")
+    ap.add_argument("--schedules", default="plain,persistent,binned,truebins")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -91,6 +165,9 @@ def main():
 
     from paper_2112_05834_amd import chem, synth
 
+    def log(msg):
+        print("bench: " + msg, file=sys.stderr, flush=True)
+
     d = tempfile.mkdtemp(prefix="chem_bench_")
     wl, mech, path, phi = synth.workload_inputs(args.workload, d)
     M = chem.Mechanism(path)
@@ -103,36 +180,61 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        print("bench: copy calibration, %d bytes read and %d bytes written" % (nb, nb), file=sys.stderr, flush=True)
+        log("copy calibration, %d bytes read and %d bytes written" % (nb, nb))
         del src, dst
     n_cells = phi.shape[0]
     n = mech.n_species + 1
     work = M.work()
-    print("bench: workload %s, %d cells, n=%d, dt=%g" % (args.workload, n_cells, n, wl.dt),
-          file=sys.stderr, flush=True)
+    log("workload %s, %d cells, n=%d, dt=%g, chain %d" % (args.workload, n_cells, n, wl.dt, args.chain))
+    scheds = args.schedules.split(",")
 
+    training = None
+    if "binned" in scheds or "truebins" in scheds:
+        training = train_model(S, chem, torch, synth, wl, mech, TRAIN_SEEDS.get(args.workload, [1040, 1041]), log)
+        log("model trained on %d samples: log %.1f s, train %.1f s, mse %.3f (target variance %.3f)" %
+            (training["samples"], training["log_s"], training["train_s"], training["mse_ln_substeps"],
+             training["target_var"]))
+
+    codes = {"plain": chem.PLAIN, "persistent": chem.PERSISTENT, "binned": chem.PERSISTENT_BINNED,
+             "truebins": chem.PERSISTENT_BINNED}
     results = {}
-    for sched in args.schedules.split(","):
-        code = {"plain": chem.PLAIN, "persistent": chem.PERSISTENT,
-                "binned": chem.PERSISTENT_BINNED}[sched]
-        r, wall, ms = time_schedule(S, chem, torch, x, wl.dt, args.steps, args.warmup, schedule=code)
+    true_cost = None
+    for sched in scheds:
+        if sched == "truebins":
+            ref = results.get("plain") or results.get("persistent") or results.get("binned")
+            if ref is None or args.chain > 1:
+                continue
+            true_cost = torch.from_numpy(np.log(np.maximum(ref["na"] + ref["nr"], 1)).astype(np.float32)).to(
+                "cuda:0")
+            S.set_cost_override(true_cost)
+        r, wall, ms, kms = time_schedule(S, chem, torch, x, wl.dt, args.steps, args.warmup, args.chain,
+                                         schedule=codes[sched])
+        used = S.last_binning_used() if codes[sched] == chem.PERSISTENT_BINNED else None
+        if sched == "truebins":
+            S.set_cost_override(None)
         na = r.n_acc.cpu().numpy().astype(np.int64)
         nr = r.n_rej.cpu().numpy().astype(np.int64)
-        st = r.status.cpu().numpy()
-        results[sched] = dict(wall=wall, ms=ms, na=na, nr=nr, status=st,
-                              cells_per_s=n_cells * args.steps / wall)
-        print("bench: %s %.1f ms/step (events %s), %.3e cells/s, failed cells %d" %
-              (sched, 1e3 * wall / args.steps, ["%.1f" % m for m in ms], n_cells * args.steps / wall,
-               int((st != 0).sum())), file=sys.stderr, flush=True)
+        stt = r.status.cpu().numpy()
+        cells = n_cells * args.steps * args.chain
+        results[sched] = dict(wall=wall, ms=ms, kms=kms, na=na, nr=nr, status=stt, used=used,
+                              cells_per_s=cells / wall)
+        log("%s %.1f ms/step (events %s), kernel ms %s, %.4e cells/s, failed cells %d, binning used %s" %
+            (sched, 1e3 * wall / (args.steps * args.chain), ["%.1f" % m for m in ms],
+             ["%.1f" % m for m in kms[:4]], cells / wall, int((stt != 0).sum()), used))
 
-    head = "binned" if "binned" in results else ("persistent" if "persistent" in results else "plain")
-    if "plain" in results and results["plain"]["cells_per_s"] > results[head]["cells_per_s"] and head != "binned":
-        head = "plain"
+    head = "binned" if "binned" in results else ("persistent" if "persistent" in results else scheds[0])
     R = results[head]
-    plain = results.get("plain", R)
-    flops = flops_per_launch(work, n, plain["na"], plain["nr"])
-    kern_s = float(np.mean(plain["ms"])) / 1e3
-    achieved = flops / kern_s
+    ref = results.get("plain", R)
+    flops = flops_per_launch(work, n, R["na"], R["nr"])
+    if args.chain > 1:
+        kern_s = achieved = None
+    else:
+        kern_s = float(np.mean(R["kms"])) / 1e3 if len(R["kms"]) else float(np.mean(R["ms"])) / 1e3
+        achieved = flops / kern_s
+    traffic = measured_traffic(os.path.join(ROOT, "paper_2112_05834_amd", "csrc", "integrator.hip"))
+    if args.workload != "spray54_262144" or args.chain > 1:
+        traffic = None
+    steps_total = args.steps * args.chain
     line = {
         "metric": METRIC,
         "value": R["cells_per_s"],
@@ -140,7 +242,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * R["wall"] / args.steps,
+        "ms_per_step": 1e3 * R["wall"] / steps_total,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -148,20 +250,28 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "cells": n_cells, "species": mech.n_species,
                    "reactions": mech.n_reactions, "pressure_Pa": wl.pressure, "dt_s": wl.dt,
-                   "schedule": head, "rtol": 1e-6, "atol": 1e-10},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK, "traffic": None,
-                     "kernel": "k_integrate (plain, one launch per chemistry step)",
-                     "flops_per_launch": flops, "kernel_ms": kern_s * 1e3},
-        "schedules": {k: {"cells_per_s": v["cells_per_s"], "ms_per_step": 1e3 * v["wall"] / args.steps}
+                   "schedule": head, "chained_steps_per_graph": args.chain, "rtol": 1e-6, "atol": 1e-10},
+        "roofline": {"bound": "alu", "achieved": None if achieved is None else achieved / 1e12,
+                     "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": None if achieved is None else achieved / FP64_VECTOR_PEAK,
+                     "traffic": traffic,
+                     "kernel": "k_integrate<%d,...> (%s schedule)" % (n, head),
+                     "flops_per_launch": flops, "kernel_ms": None if kern_s is None else kern_s * 1e3},
+        "schedules": {k: {"cells_per_s": v["cells_per_s"], "ms_per_step": 1e3 * v["wall"] / steps_total,
+                          "kernel_ms": float(np.mean(v["kms"])) if len(v["kms"]) else None,
+                          "binning_used": v["used"]}
                       for k, v in results.items()},
-        "substeps": {"mean": float((plain["na"] + plain["nr"]).mean()),
-                     "p50": float(np.percentile(plain["na"] + plain["nr"], 50)),
-                     "p99": float(np.percentile(plain["na"] + plain["nr"], 99)),
-                     "max": int((plain["na"] + plain["nr"]).max())},
+        "substeps": {"mean": float((ref["na"] + ref["nr"]).mean()),
+                     "p50": float(np.percentile(ref["na"] + ref["nr"], 50)),
+                     "p99": float(np.percentile(ref["na"] + ref["nr"], 99)),
+                     "max": int((ref["na"] + ref["nr"]).max())},
     }
+    if "plain" in results and head != "plain":
+        line["speedup_vs_plain"] = R["cells_per_s"] / results["plain"]["cells_per_s"]
+    if training is not None:
+        line["training"] = training
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(path, phi, wl.dt, args.cpu_sample, 7)
+        line["cpu_baseline"] = cpu_baseline(path, phi, wl.dt, args.cpu_seconds, 7)
     print(json.dumps(line), flush=True)
 
 

@@ -184,16 +184,43 @@ int chem_model_train(chem_solver* s, int64_t n, const float* feats_dev, const fl
 /* Predicted ln substeps for n cells' features (device float32 in / out). */
 int chem_model_predict(chem_solver* s, int64_t n, const float* feats_dev, float* pred_dev,
                        void* stream);
-/* Use given per-cell costs (device float32 [n_cells]) instead of the model's
- * prediction for the next binned chem_integrate call on exactly n_cells cells
- * (for comparison against bins sorted by true cost); NULL clears. */
+/* Use given per-cell costs (device float32 [n_cells], same unit as the
+ * prediction: ln substeps) instead of the model's prediction for binned
+ * calls on exactly n_cells cells, binned with the model's edges (for
+ * comparison against bins sorted by true cost); NULL clears. The buffer must
+ * stay valid while set. Without model edges the queue order is used. */
 int chem_set_cost_override(chem_solver* s, int64_t n_cells, const float* cost_dev);
 /* Model state as a file: weights (FP32 master), normalisation, bin edges. */
 int chem_model_save(const chem_solver* s, const char* path);
 int chem_model_load(chem_solver* s, const char* path);
-/* Whether the last binned launch used the model (1) or fell back to queue
- * order (0: no trained model, or a non-finite prediction). Host value. */
+/* Whether the last binned launch used the model or an override (1) or fell
+ * back to queue order (0: no model, or a non-finite cost, detected on the
+ * device). Reads a device flag: synchronises with the device. */
 int chem_last_binning_used(const chem_solver* s, int32_t* used);
+
+/* Model weights in host memory: params [4545] float32 in the order
+ * W1 [64][4], b1 [64], W2 [64][64], b2 [64], w3 [64], b3 (row = output
+ * unit); norm [8] = feature means [4] then standard deviations [4]; edges [7]
+ * ascending bin edges. get: any pointer may be NULL; CHEM_ESTATE without
+ * weights (or without edges when edges is requested). set: norm NULL means
+ * means 0 and deviations 1; edges NULL leaves the model without edges. */
+int chem_model_get(const chem_solver* s, float* params, float* norm, float* edges);
+int chem_model_set(chem_solver* s, const float* params, const float* norm, const float* edges);
+/* Mean squared error and its gradient (float32 [4545], device) of the
+ * current weights over n samples taken as one minibatch (features and
+ * targets as for chem_model_train); loss_dev: one float (device). */
+int chem_model_grad(chem_solver* s, int64_t n, const float* feats_dev, const float* target_dev,
+                    float* grad_dev, float* loss_dev, void* stream);
+/* The seven octile edges of n finite costs (device float32): the values at
+ * ascending sorted positions floor(k n / 8), k = 1..7, written to host
+ * edges[7]. Synchronises the stream. */
+int chem_bin_edges(chem_solver* s, int64_t n, const float* cost_dev, float* edges, void* stream);
+/* Queue order for n costs (device float32): cells of bin 7 (cost >= edges[6])
+ * first down to bin 0, cell index ascending within a bin; identity when any
+ * cost is not finite. edges: host [7], NULL = the model's. perm_dev: device
+ * int32 [n], caller-owned. */
+int chem_bin_order(chem_solver* s, int64_t n, const float* cost_dev, const float* edges, int32_t* perm_dev,
+                   void* stream);
 
 /* ---- autotuning --------------------------------------------------------- */
 
@@ -204,6 +231,17 @@ int chem_last_binning_used(const chem_solver* s, int32_t* used);
  * shapes). */
 int chem_autotune(chem_solver* s, int64_t n_sample, const double* phi_sample_dev, double dt,
                   void* stream);
+
+/* ---- kernel timing ---------------------------------------------------- */
+
+/* enable != 0: from now on record a pair of HIP events on the caller's
+ * stream around every integration-kernel launch made outside graph capture
+ * (clears earlier records); enable == 0: stop recording and free them. */
+int chem_kernel_timing(chem_solver* s, int32_t enable);
+/* Wait for the recorded launches and write their durations in milliseconds
+ * (launch order, at most cap) to host ms_out; *n_out = number written. The
+ * records are cleared. */
+int chem_kernel_times(chem_solver* s, float* ms_out, int32_t cap, int32_t* n_out);
 
 const char* chem_last_error(void);
 

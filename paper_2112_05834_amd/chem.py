@@ -42,6 +42,8 @@ class TrainOpts(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
+N_MODEL_PARAMS = 4545
+
 _lib = None
 _vp = ctypes.c_void_p
 
@@ -79,7 +81,14 @@ def lib():
             "chem_model_save": (i32, [_vp, ctypes.c_char_p]),
             "chem_model_load": (i32, [_vp, ctypes.c_char_p]),
             "chem_last_binning_used": (i32, [_vp, ctypes.POINTER(i32)]),
+            "chem_model_get": (i32, [_vp, _vp, _vp, _vp]),
+            "chem_model_set": (i32, [_vp, _vp, _vp, _vp]),
+            "chem_model_grad": (i32, [_vp, i64, _vp, _vp, _vp, _vp, _vp]),
+            "chem_bin_edges": (i32, [_vp, i64, _vp, _vp, _vp]),
+            "chem_bin_order": (i32, [_vp, i64, _vp, _vp, _vp, _vp]),
             "chem_autotune": (i32, [_vp, i64, _vp, dbl, _vp]),
+            "chem_kernel_timing": (i32, [_vp, i32]),
+            "chem_kernel_times": (i32, [_vp, _vp, i32, ctypes.POINTER(i32)]),
             "chem_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -305,6 +314,70 @@ class Solver:
         u = ctypes.c_int32()
         _check(lib().chem_last_binning_used(self._h, ctypes.byref(u)))
         return bool(u.value)
+
+    def model_get(self):
+        """(params [4545], norm [8], edges [7] or None) as float32 numpy arrays."""
+        import numpy as np
+        p = np.empty(N_MODEL_PARAMS, dtype=np.float32)
+        nv = np.empty(8, dtype=np.float32)
+        _check(lib().chem_model_get(self._h, p.ctypes.data_as(_vp), nv.ctypes.data_as(_vp), None))
+        e = np.empty(7, dtype=np.float32)
+        rc = lib().chem_model_get(self._h, None, None, e.ctypes.data_as(_vp))
+        return p, nv, (e if rc == 0 else None)
+
+    def model_set(self, params, norm=None, edges=None):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != N_MODEL_PARAMS:
+            raise ValueError("params must have %d elements" % N_MODEL_PARAMS)
+        nv = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32)
+        e = None if edges is None else np.ascontiguousarray(edges, dtype=np.float32)
+        if nv is not None and nv.size != 8:
+            raise ValueError("norm must have 8 elements")
+        if e is not None and e.size != 7:
+            raise ValueError("edges must have 7 elements")
+        _check(lib().chem_model_set(self._h, p.ctypes.data_as(_vp),
+                                    None if nv is None else nv.ctypes.data_as(_vp),
+                                    None if e is None else e.ctypes.data_as(_vp)))
+
+    def model_grad(self, feats: torch.Tensor, target: torch.Tensor):
+        """(loss, gradient [4545]) of the current weights over all samples as one batch."""
+        n = feats.shape[0]
+        g = torch.empty(N_MODEL_PARAMS, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(lib().chem_model_grad(self._h, n, _ptr(feats, torch.float32, self.device, 4 * n, "feats"),
+                                     _ptr(target, torch.float32, self.device, n, "target"), _ptr(g), _ptr(loss),
+                                     _stream(self.device)))
+        return loss, g
+
+    def bin_edges(self, cost: torch.Tensor):
+        import numpy as np
+        e = np.empty(7, dtype=np.float32)
+        _check(lib().chem_bin_edges(self._h, cost.numel(), _ptr(cost, torch.float32, self.device, name="cost"),
+                                    e.ctypes.data_as(_vp), _stream(self.device)))
+        return e
+
+    def bin_order(self, cost: torch.Tensor, edges=None) -> torch.Tensor:
+        import numpy as np
+        n = cost.numel()
+        perm = torch.empty(n, dtype=torch.int32, device=self.device)
+        e = None if edges is None else np.ascontiguousarray(edges, dtype=np.float32)
+        _check(lib().chem_bin_order(self._h, n, _ptr(cost, torch.float32, self.device, name="cost"),
+                                    None if e is None else e.ctypes.data_as(_vp), _ptr(perm),
+                                    _stream(self.device)))
+        return perm
+
+    def kernel_timing(self, enable: bool):
+        _check(lib().chem_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_times(self, cap: int = 4096):
+        """Durations (ms) of the integration-kernel launches recorded since
+        kernel_timing(True); clears the record."""
+        import numpy as np
+        a = np.empty(max(cap, 1), dtype=np.float32)
+        n = ctypes.c_int32()
+        _check(lib().chem_kernel_times(self._h, a.ctypes.data_as(_vp), cap, ctypes.byref(n)))
+        return a[:n.value].astype(np.float64)
 
     def autotune(self, phi_sample: torch.Tensor, dt: float):
         _check(lib().chem_autotune(self._h, phi_sample.shape[0],

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/chem.h"
@@ -91,6 +92,9 @@ struct chem_solver {
   int last_binning_used = 0;
   const float* cost_override = nullptr;
   int64_t cost_override_n = 0;
+  // kernel timing: event pairs around integration launches
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
   // logging
   float* log_feats = nullptr;
   float* log_target = nullptr;
@@ -212,6 +216,14 @@ int chem_solver_create(const chem_mech* m, const chem_opts* o, int32_t dev, chem
   return CHEM_OK;
 }
 
+static void clear_timing(chem_solver* s) {
+  for (auto& e : s->tev) {
+    hipEventDestroy(e.first);
+    hipEventDestroy(e.second);
+  }
+  s->tev.clear();
+}
+
 static void drop_graph(chem_solver* s) {
   if (s->graph) hipGraphExecDestroy(s->graph);
   if (s->graph_src) hipGraphDestroy(s->graph_src);
@@ -225,6 +237,7 @@ void chem_solver_free(chem_solver* s) {
   DeviceGuard g(s->dev);
   hipDeviceSynchronize();
   drop_graph(s);
+  clear_timing(s);
   chem_model::release(s->model);
   hipFree(s->d_blob);
   hipFree(s->d_nasa);
@@ -349,7 +362,21 @@ int launch_step(chem_solver* s, const chem_opts& o, int64_t n, double dt, const 
   }
   if (grid < 1) return CHEM_OK;
   if (grid > 0x7fffffffLL) return fail(CHEM_EINVAL, "too many cells for one launch");
+  bool timed = false;
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (s->timing) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cs), "hipStreamIsCapturing");
+    if (cs == hipStreamCaptureStatusNone) {
+      HIP_TRY(hipEventCreate(&ev.first), "hipEventCreate");
+      HIP_TRY(hipEventCreate(&ev.second), "hipEventCreate");
+      s->tev.push_back(ev);
+      HIP_TRY(hipEventRecord(ev.first, st), "hipEventRecord");
+      timed = true;
+    }
+  }
   HIP_TRY(chemk::launch_integrate(sh.v, persistent, static_cast<int>(grid), a, sh.lds, st), "integrate launch");
+  if (timed) HIP_TRY(hipEventRecord(ev.second, st), "hipEventRecord");
   return CHEM_OK;
 }
 
@@ -357,11 +384,17 @@ int binned_perm(chem_solver* s, int64_t n, double dt, const double* in, hipStrea
   *perm = nullptr;
   int used = 0;
   const float* over = (s->cost_override && s->cost_override_n == n) ? s->cost_override : nullptr;
-  int rc = chem_model::plan(s->model, s->margs, s->nvariants ? s->variants[0] : chemk::Variant{0, 0}, n, dt, in,
-                            over, st, perm, &used);
+  int rc = chem_model::plan(s->model, s->margs, n, dt, in, over, st, perm, &used);
   if (rc) return fail(rc, chem_model::last_error());
   s->last_binning_used = used;
   return CHEM_OK;
+}
+
+// binning buffers for n cells (allocation happens here, never under capture)
+int reserve_binning(chem_solver* s, int64_t n) {
+  if (s->opts.schedule != CHEM_PERSISTENT_BINNED) return CHEM_OK;
+  int rc = chem_model::reserve(s->model, n);
+  return rc ? fail(rc, chem_model::last_error()) : CHEM_OK;
 }
 
 }  // namespace
@@ -376,6 +409,7 @@ int chem_integrate(chem_solver* s, int64_t n, double dt, const double* in, doubl
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int* perm = nullptr;
   if (s->opts.schedule == CHEM_PERSISTENT_BINNED) {
+    if (int rc = reserve_binning(s, n)) return rc;
     if (int rc = binned_perm(s, n, dt, in, st, &perm)) return rc;
   }
   return launch_step(s, s->opts, n, dt, in, out, h_io, n_acc, n_rej, status, 0, perm, st);
@@ -388,6 +422,7 @@ int chem_integrate_steps(chem_solver* s, int32_t n_steps, int64_t n, double dt, 
   if (n == 0) return CHEM_OK;
   if (in == out && n_steps > 1) return fail(CHEM_EINVAL, "chem_integrate_steps: phi_in must not alias phi_out");
   DeviceGuard g(s->dev);
+  if (int rc = reserve_binning(s, n)) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t w = static_cast<size_t>(s->ns) + 2;
   if (s->ping_cells < static_cast<size_t>(n) && n_steps > 1) {
@@ -611,8 +646,50 @@ int chem_model_load(chem_solver* s, const char* path) {
 
 int chem_last_binning_used(const chem_solver* s, int32_t* used) {
   if (!s || !used) return fail(CHEM_EINVAL, "chem_last_binning_used: bad argument");
-  *used = s->last_binning_used;
+  *used = 0;
+  if (!s->last_binning_used) return CHEM_OK;
+  DeviceGuard g(s->dev);
+  int fin = 0;
+  if (int rc = chem_model::last_plan_finite(s->model, &fin)) return fail(rc, chem_model::last_error());
+  *used = fin ? 1 : 0;
   return CHEM_OK;
+}
+
+int chem_model_get(const chem_solver* s, float* params, float* norm, float* edges) {
+  if (!s) return fail(CHEM_EINVAL, "chem_model_get: bad argument");
+  DeviceGuard g(s->dev);
+  int rc = chem_model::get_params(s->model, params, norm, edges);
+  return rc ? fail(rc, chem_model::last_error()) : CHEM_OK;
+}
+
+int chem_model_set(chem_solver* s, const float* params, const float* norm, const float* edges) {
+  if (!s || !params) return fail(CHEM_EINVAL, "chem_model_set: bad argument");
+  DeviceGuard g(s->dev);
+  drop_graph(s);
+  int rc = chem_model::set_params(s->model, params, norm, edges);
+  return rc ? fail(rc, chem_model::last_error()) : CHEM_OK;
+}
+
+int chem_model_grad(chem_solver* s, int64_t n, const float* feats, const float* target, float* grad, float* loss,
+                    void* stream) {
+  if (!s || n < 1 || !feats || !target || !grad || !loss) return fail(CHEM_EINVAL, "chem_model_grad: bad argument");
+  DeviceGuard g(s->dev);
+  int rc = chem_model::grad(s->model, n, feats, target, grad, loss, static_cast<hipStream_t>(stream));
+  return rc ? fail(rc, chem_model::last_error()) : CHEM_OK;
+}
+
+int chem_bin_edges(chem_solver* s, int64_t n, const float* cost, float* edges, void* stream) {
+  if (!s || n < 1 || !cost || !edges) return fail(CHEM_EINVAL, "chem_bin_edges: bad argument");
+  DeviceGuard g(s->dev);
+  int rc = chem_model::octiles(s->model, n, cost, edges, static_cast<hipStream_t>(stream));
+  return rc ? fail(rc, chem_model::last_error()) : CHEM_OK;
+}
+
+int chem_bin_order(chem_solver* s, int64_t n, const float* cost, const float* edges, int32_t* perm, void* stream) {
+  if (!s || n < 1 || !cost || !perm) return fail(CHEM_EINVAL, "chem_bin_order: bad argument");
+  DeviceGuard g(s->dev);
+  int rc = chem_model::order(s->model, n, cost, edges, perm, static_cast<hipStream_t>(stream));
+  return rc ? fail(rc, chem_model::last_error()) : CHEM_OK;
 }
 
 // ---- autotuning ------------------------------------------------------------
@@ -670,6 +747,34 @@ int chem_autotune(chem_solver* s, int64_t n_sample, const double* phi, double dt
   best.blocks = s->opts.blocks;
   s->opts = best;
   drop_graph(s);
+  return CHEM_OK;
+}
+
+// ---- kernel timing -----------------------------------------------------------
+
+int chem_kernel_timing(chem_solver* s, int32_t enable) {
+  if (!s) return fail(CHEM_EINVAL, "chem_kernel_timing: bad argument");
+  DeviceGuard g(s->dev);
+  if (!s->tev.empty()) HIP_TRY(hipEventSynchronize(s->tev.back().second), "hipEventSynchronize");
+  clear_timing(s);
+  s->timing = enable != 0;
+  return CHEM_OK;
+}
+
+int chem_kernel_times(chem_solver* s, float* ms, int32_t cap, int32_t* n_out) {
+  if (!s || !n_out || cap < 0 || (cap > 0 && !ms)) return fail(CHEM_EINVAL, "chem_kernel_times: bad argument");
+  DeviceGuard g(s->dev);
+  int32_t k = 0;
+  for (auto& e : s->tev) {
+    HIP_TRY(hipEventSynchronize(e.second), "hipEventSynchronize");
+    if (k < cap) {
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, e.first, e.second), "hipEventElapsedTime");
+      ms[k++] = t;
+    }
+  }
+  clear_timing(s);
+  *n_out = k;
   return CHEM_OK;
 }
 
