@@ -92,6 +92,15 @@ struct chem_solver {
   int last_binning_used = 0;
   const float* cost_override = nullptr;
   int64_t cost_override_n = 0;
+  // workgroup-per-cell kernel (state sizes above one wave): per-slot HBM
+  // workspace for J and M, one slot per resident workgroup
+  bool wide = false;
+  int ld = 0;
+  size_t wide_lds = 0;
+  int wide_slots = 0;
+  int64_t wide_budget = -1;      // budget the slots were sized for
+  double* d_ws = nullptr;
+  long long ws_stride = 0;       // doubles per slot
   // kernel timing: event pairs around integration launches
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
@@ -177,6 +186,13 @@ int chem_solver_create(const chem_mech* m, const chem_opts* o, int32_t dev, chem
   s->n = s->ns + 1;
   s->work = m->work;
   s->nvariants = chemk::variants_for(s->n, s->variants, 8);
+  if (s->nvariants == 0 && s->n <= chemk::kWideNN) {
+    s->wide = true;
+    s->variants[0] = chemk::Variant{chemk::kWideNN, chemk::kWideThreads};
+    s->nvariants = 1;
+    s->ld = chemk::wide_ld(s->n);
+    s->ws_stride = 2LL * s->n * s->ld;
+  }
   if (s->nvariants == 0)
     return fail(CHEM_EUNSUPPORTED, "no compiled kernel for state size " + std::to_string(s->n));
   DeviceGuard g(dev);
@@ -211,6 +227,11 @@ int chem_solver_create(const chem_mech* m, const chem_opts* o, int32_t dev, chem
   a.nasa = s->d_nasa;
   a.W = s->d_W;
   if (int rc = chem_model::init(s->model)) return fail(rc, chem_model::last_error());
+  if (s->wide) {
+    s->wide_lds = static_cast<size_t>(a.lds_bytes) + chemk::wide_cell_bytes(s->ns, s->nr, s->ld);
+    if (s->wide_lds > kMaxLds)
+      return fail(CHEM_EUNSUPPORTED, "mechanism and one cell's work area exceed the 160 KB LDS");
+  }
   HIP_TRY(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
   *out = s.release();
   return CHEM_OK;
@@ -244,6 +265,7 @@ void chem_solver_free(chem_solver* s) {
   hipFree(s->d_W);
   hipFree(s->d_head);
   hipFree(s->d_ping);
+  hipFree(s->d_ws);
   hipFree(s->log_feats);
   hipFree(s->log_target);
   if (s->capture_stream) hipStreamDestroy(s->capture_stream);
@@ -278,6 +300,15 @@ struct Shape {
 };
 
 int pick_shape(const chem_solver* s, const chem_opts& o, Shape& sh) {
+  if (s->wide) {
+    if (o.cells_per_wave > 1)
+      return fail(CHEM_EUNSUPPORTED, "state size " + std::to_string(s->n) + " runs one cell per workgroup");
+    sh.v = s->variants[0];
+    sh.cpw = 1;
+    sh.wpb = chemk::kWideThreads / 64;
+    sh.lds = s->wide_lds;
+    return CHEM_OK;
+  }
   // variant by requested cells per wave, else the first compiled one
   int want_g = o.cells_per_wave > 0 ? 64 / o.cells_per_wave : 0;
   sh.v = s->variants[0];
@@ -318,6 +349,36 @@ int check_integrate_args(const chem_solver* s, int64_t n, double dt, const doubl
   return CHEM_OK;
 }
 
+// Workspace slots of the workgroup kernel: one per resident workgroup, at
+// most hbm_budget_bytes (default: half the free device memory) in total.
+// Allocates; never called under stream capture.
+int ensure_ws(chem_solver* s) {
+  if (!s->wide) return CHEM_OK;
+  const int64_t budget_opt = s->opts.hbm_budget_bytes;
+  if (s->d_ws && s->wide_budget == budget_opt) return CHEM_OK;
+  int bpc = chemk::integrate_wide_blocks_per_cu(true, s->wide_lds);
+  if (bpc < 1) bpc = 1;
+  const long long cap = static_cast<long long>(s->cus) * bpc;
+  int64_t budget = budget_opt;
+  if (budget <= 0) {
+    size_t fr = 0, tot = 0;
+    HIP_TRY(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+    budget = static_cast<int64_t>(fr / 2) + (s->d_ws ? static_cast<int64_t>(s->wide_slots) * s->ws_stride * 8 : 0);
+  }
+  const long long slot_bytes = s->ws_stride * static_cast<long long>(sizeof(double));
+  long long slots = budget / slot_bytes;
+  if (slots > cap) slots = cap;
+  if (slots < 1) return fail(CHEM_ENOMEM, "hbm_budget_bytes is below one cell's workspace");
+  hipFree(s->d_ws);
+  s->d_ws = nullptr;
+  s->wide_slots = 0;
+  drop_graph(s);
+  HIP_TRY(hipMalloc(&s->d_ws, static_cast<size_t>(slots) * slot_bytes), "hipMalloc workspace");
+  s->wide_slots = static_cast<int>(slots);
+  s->wide_budget = budget_opt;
+  return CHEM_OK;
+}
+
 // One chemistry step with the solver's options on stream st.
 int launch_step(chem_solver* s, const chem_opts& o, int64_t n, double dt, const double* in, double* out,
                 double* h_io, int32_t* n_acc, int32_t* n_rej, int8_t* status, int accumulate,
@@ -350,7 +411,16 @@ int launch_step(chem_solver* s, const chem_opts& o, int64_t n, double dt, const 
   const bool persistent = o.schedule != CHEM_PLAIN;
   const long long per_block = static_cast<long long>(sh.wpb) * sh.cpw;
   long long grid;
-  if (!persistent) {
+  if (s->wide) {
+    if (!s->d_ws) return fail(CHEM_ESTATE, "workspace not allocated");
+    a.ws = s->d_ws;
+    a.ws_stride = s->ws_stride;
+    a.ld = s->ld;
+    grid = s->wide_slots;
+    if (o.blocks > 0 && o.blocks < grid) grid = o.blocks;
+    if (grid > n) grid = n;
+    if (persistent) HIP_TRY(chemk::launch_fill_u64(s->d_head, 0ull, st), "queue reset");
+  } else if (!persistent) {
     grid = (n + per_block - 1) / per_block;
   } else {
     int bpc = chemk::integrate_blocks_per_cu(sh.v, true, sh.wpb, sh.lds);
@@ -375,7 +445,11 @@ int launch_step(chem_solver* s, const chem_opts& o, int64_t n, double dt, const 
       timed = true;
     }
   }
-  HIP_TRY(chemk::launch_integrate(sh.v, persistent, static_cast<int>(grid), a, sh.lds, st), "integrate launch");
+  if (s->wide) {
+    HIP_TRY(chemk::launch_integrate_wide(persistent, static_cast<int>(grid), a, sh.lds, st), "integrate launch");
+  } else {
+    HIP_TRY(chemk::launch_integrate(sh.v, persistent, static_cast<int>(grid), a, sh.lds, st), "integrate launch");
+  }
   if (timed) HIP_TRY(hipEventRecord(ev.second, st), "hipEventRecord");
   return CHEM_OK;
 }
@@ -407,6 +481,7 @@ int chem_integrate(chem_solver* s, int64_t n, double dt, const double* in, doubl
   if (n == 0) return CHEM_OK;
   DeviceGuard g(s->dev);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int rc = ensure_ws(s)) return rc;
   const int* perm = nullptr;
   if (s->opts.schedule == CHEM_PERSISTENT_BINNED) {
     if (int rc = reserve_binning(s, n)) return rc;
@@ -423,6 +498,7 @@ int chem_integrate_steps(chem_solver* s, int32_t n_steps, int64_t n, double dt, 
   if (in == out && n_steps > 1) return fail(CHEM_EINVAL, "chem_integrate_steps: phi_in must not alias phi_out");
   DeviceGuard g(s->dev);
   if (int rc = reserve_binning(s, n)) return rc;
+  if (int rc = ensure_ws(s)) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t w = static_cast<size_t>(s->ns) + 2;
   if (s->ping_cells < static_cast<size_t>(n) && n_steps > 1) {
@@ -517,8 +593,17 @@ int chem_eval_rhs_jac(chem_solver* s, int64_t n, const double* phi, double* f, d
   a.phi = phi;
   a.f = f;
   a.J = J;
-  a.cell_doubles = chemk::cell_doubles(sh.v.nn, s->nr, s->ns);
   a.wpb = sh.wpb;
+  if (s->wide) {
+    if (int rc = ensure_ws(s)) return rc;
+    a.ws = s->d_ws;
+    a.ws_stride = s->ws_stride;
+    a.ld = s->ld;
+    const long long grid = n < s->wide_slots ? n : s->wide_slots;
+    HIP_TRY(chemk::launch_eval_wide(static_cast<int>(grid), a, sh.lds, static_cast<hipStream_t>(stream)), "eval launch");
+    return CHEM_OK;
+  }
+  a.cell_doubles = chemk::cell_doubles(sh.v.nn, s->nr, s->ns);
   const long long per_block = static_cast<long long>(sh.wpb) * sh.cpw;
   const long long grid = (n + per_block - 1) / per_block;
   HIP_TRY(chemk::launch_eval(sh.v, static_cast<int>(grid), a, sh.lds, static_cast<hipStream_t>(stream)), "eval launch");
@@ -539,6 +624,16 @@ int chem_lu_batch(chem_solver* s, int64_t batch, double* A, int32_t* piv, int32_
   a.info = info;
   a.b = b;
   a.wpb = 4;
+  if (s->wide) {
+    if (int rc = ensure_ws(s)) return rc;
+    a.ws = s->d_ws;
+    a.ws_stride = s->ws_stride;
+    a.ld = s->ld;
+    const long long grid = batch < s->wide_slots ? batch : s->wide_slots;
+    const size_t lds = chemk::wide_cell_bytes(0, 0, s->ld);
+    HIP_TRY(chemk::launch_lu_wide(static_cast<int>(grid), a, lds, static_cast<hipStream_t>(stream)), "lu launch");
+    return CHEM_OK;
+  }
   const long long per_block = 4LL * sh.cpw;
   const long long grid = (batch + per_block - 1) / per_block;
   HIP_TRY(chemk::launch_lu(sh.v, static_cast<int>(grid), a, static_cast<hipStream_t>(stream)), "lu launch");
@@ -698,6 +793,7 @@ int chem_autotune(chem_solver* s, int64_t n_sample, const double* phi, double dt
   if (!s || n_sample < 1 || !phi || !(dt > 0)) return fail(CHEM_EINVAL, "chem_autotune: bad argument");
   DeviceGuard g(s->dev);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int rc = ensure_ws(s)) return rc;
   const size_t w = static_cast<size_t>(s->ns) + 2;
   double* out = nullptr;
   double* h = nullptr;

@@ -11,32 +11,19 @@
 // grid or on the schedule: reductions follow one fixed pairing tree over 64
 // virtual lanes, pivots are chosen by value then lowest position, and every
 // other operation is per element in a fixed order.
-#include "kernels.hpp"
-
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdint>
 
+#include "device_common.hpp"
+#include "kernels.hpp"
+
 namespace chemk {
 
 namespace {
 
-constexpr double kR = 8.314462618;     // J mol^-1 K^-1
-constexpr double kPatm = 101325.0;     // Pa
-constexpr double kLn10 = 2.302585092994045684;
-constexpr int kBig = 1 << 20;
-
-// Rodas3 in the transformed form (unknowns u_i, matrix I/(gamma h) - J):
-// u_s = M^-1 ( f(y + sum_j a_sj u_j) + sum_j (c_sj / h) u_j ), y_new = y + sum m_j u_j,
-// error estimate u_4.
-constexpr double kGamma = 0.5;
-constexpr double kA31 = 2.0, kA41 = 2.0, kA43 = 1.0;
-constexpr double kC21 = 4.0, kC31 = 1.0, kC32 = -1.0, kC41 = 1.0, kC42 = -1.0;
-constexpr double kC43 = -8.0 / 3.0;
-// step-size controller
-constexpr double kFacMin = 0.2, kFacMax = 6.0, kFacSafe = 0.9, kFacRej = 0.1;
-constexpr double kHMin = 1e-20, kTMin = 200.0, kTMax = 6000.0;
+using namespace dev;
 
 // LDS accesses of one wave stay ordered; keep the compiler from moving them
 // across a point where other lanes' writes must be visible.
@@ -158,38 +145,6 @@ struct Grp {
   }
 };
 
-// ---------------------------------------------------------------------------
-// mechanism in LDS
-// ---------------------------------------------------------------------------
-struct MechLds {
-  const double *lnA, *b, *EaR, *troe, *eff_am1, *rW;
-  const uint4* rint;
-  const uint16_t *eff_sp, *sp_off, *sp_ent;
-};
-
-__device__ __forceinline__ MechLds mech_views(const unsigned char* s, const MechArgs& m) {
-  MechLds L;
-  const unsigned char* g = reinterpret_cast<const unsigned char*>(m.blob);
-  L.lnA = reinterpret_cast<const double*>(g + m.off_lnA);
-  L.b = reinterpret_cast<const double*>(g + m.off_b);
-  L.EaR = reinterpret_cast<const double*>(g + m.off_EaR);
-  L.troe = reinterpret_cast<const double*>(g + m.off_troe);
-  L.rint = reinterpret_cast<const uint4*>(s + m.off_rint);
-  L.eff_am1 = reinterpret_cast<const double*>(s + m.off_eff_am1);
-  L.eff_sp = reinterpret_cast<const uint16_t*>(s + m.off_eff_sp);
-  L.sp_off = reinterpret_cast<const uint16_t*>(s + m.off_sp_off);
-  L.sp_ent = reinterpret_cast<const uint16_t*>(s + m.off_sp_ent);
-  L.rW = reinterpret_cast<const double*>(s + m.off_rW);
-  return L;
-}
-
-__device__ __forceinline__ void stage_mech(unsigned char* smem, const MechArgs& m) {
-  uint4* d = reinterpret_cast<uint4*>(smem);
-  const int n16 = m.lds_bytes / 16;
-  for (int i = threadIdx.x; i < n16; i += blockDim.x) d[i] = m.blob[i];
-  __syncthreads();
-}
-
 // Per-cell LDS area layout (doubles): J [NN*NN] row-major, pivot-row buffer
 // P [NN+1 rounded to even], per-reaction buffers RB [5*nr] (rate of progress,
 // and with the Jacobian kf*theta, kr*theta, q0*dtheta/d[M], dq/dT), then the
@@ -218,38 +173,6 @@ __device__ __forceinline__ CellArea cell_area(double* base, int nr, int ns) {
   c.gRT = c.C + ns;
   c.hRT = c.gRT + ns;
   return c;
-}
-
-// Mass-action product of one reaction side (up to 3 distinct species with
-// orders 1..3) and its partial derivative by each species, without division
-// by a concentration; branch-free (absent slots read species 0 and count as
-// order 0). sg accumulates sign * order * g/RT of the side's species.
-__device__ __forceinline__ void mass_action(const double* C, unsigned spw, unsigned ordw, int k,
-                                            double& P, double (&dP)[3], int (&sp)[3]) {
-  double pw[3], dp[3], cc[3];
-  int oo[3];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const bool on = j < k;
-    sp[j] = on ? (spw >> (8 * j)) & 0xff : 0;
-    oo[j] = on ? (ordw >> (4 * j)) & 0xf : 0;
-    cc[j] = C[sp[j]];
-  }
-  // keep the three loads together (one LDS round trip) rather than sunk
-  // into per-slot branches
-  asm volatile("" : "+v"(cc[0]), "+v"(cc[1]), "+v"(cc[2]));
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const int o = oo[j];
-    const double c = cc[j];
-    const double c2 = c * c;
-    pw[j] = o == 0 ? 1.0 : (o == 1 ? c : (o == 2 ? c2 : c2 * c));
-    dp[j] = o == 0 ? 0.0 : (o == 1 ? 1.0 : (o == 2 ? 2.0 * c : 3.0 * c2));
-  }
-  P = pw[0] * pw[1] * pw[2];
-  dP[0] = dp[0] * pw[1] * pw[2];
-  dP[1] = pw[0] * dp[1] * pw[2];
-  dP[2] = pw[0] * pw[1] * dp[2];
 }
 
 // ---------------------------------------------------------------------------
@@ -284,14 +207,9 @@ struct Cell {
     // species thermo (NASA-7, range by T < Tmid)
     double cpR = 0.0, hRT = 0.0, dcpR = 0.0;
     if (sp) {
-      const double* a = A.nasa + 16 * s;
-      if (!(T < a[7])) a += 8;
-      const double a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3], a4 = a[4], a5 = a[5], a6 = a[6];
-      cpR = fma(T, fma(T, fma(T, fma(T, a4, a3), a2), a1), a0);
-      hRT = fma(T, fma(T, fma(T, fma(T, a4 * 0.2, a3 * 0.25), a2 * (1.0 / 3.0)), a1 * 0.5), a0) + a5 * rT;
-      const double sR = fma(a0, lnT, fma(T, fma(T, fma(T, a4 * 0.25, a3 * (1.0 / 3.0)), a2 * 0.5), a1) * T) + a6;
-      if (JAC) dcpR = fma(T, fma(T, 4.0 * a4, 3.0 * a3), 2.0 * a2) * T + a1;
-      ca.gRT[s] = hRT - sR;
+      double gRT;
+      nasa7<JAC>(A.nasa + 16 * s, T, rT, lnT, cpR, hRT, gRT, dcpR);
+      ca.gRT[s] = gRT;
       ca.hRT[s] = hRT;
     }
     const double cp = Gp::sum(Ys * cpR * kR * rWs);
@@ -310,111 +228,7 @@ struct Cell {
     for (int r0 = 0; r0 < nr; r0 += G) {
       const int rx = r0 + i;
       if (rx >= nr) break;
-      const uint4 w = L.rint[rx];
-      const int type = (w.x >> 28) & 3;
-      const bool rev = (w.x >> 30) & 1;
-      const int nre = (w.x >> 24) & 0xf, npr = (w.y >> 24) & 0xf;
-      const int dnu = static_cast<int>((w.z >> 24) & 0x7f) - 64;
-      const double bb = L.b[rx], ear = L.EaR[rx];
-      const double lnkf = L.lnA[rx] + bb * lnT - ear * rT;
-      const double kf = exp(lnkf);
-      double Pf, Pr, sumg = 0.0, sumh = 0.0;
-      {
-        double pw[3], pr[3], cf[3], cr[3], gf[3], gr[3], hf[3], hr[3];
-        int of[3], orr[3];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const bool onf = j < nre, onr = j < npr;
-          const int qf = onf ? (w.x >> (8 * j)) & 0xff : 0;
-          const int qr = onr ? (w.y >> (8 * j)) & 0xff : 0;
-          of[j] = onf ? (w.z >> (4 * j)) & 0xf : 0;
-          orr[j] = onr ? (w.z >> (12 + 4 * j)) & 0xf : 0;
-          cf[j] = ca.C[qf];
-          cr[j] = ca.C[qr];
-          gf[j] = ca.gRT[qf];
-          gr[j] = ca.gRT[qr];
-          hf[j] = JAC ? ca.hRT[qf] : 0.0;
-          hr[j] = JAC ? ca.hRT[qr] : 0.0;
-        }
-        // one LDS round trip for all species data of the reaction
-        asm volatile("" : "+v"(cf[0]), "+v"(cf[1]), "+v"(cf[2]), "+v"(cr[0]), "+v"(cr[1]), "+v"(cr[2]));
-        asm volatile("" : "+v"(gf[0]), "+v"(gf[1]), "+v"(gf[2]), "+v"(gr[0]), "+v"(gr[1]), "+v"(gr[2]));
-        if (JAC) asm volatile("" : "+v"(hf[0]), "+v"(hf[1]), "+v"(hf[2]), "+v"(hr[0]), "+v"(hr[1]), "+v"(hr[2]));
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const double cf2 = cf[j] * cf[j], cr2 = cr[j] * cr[j];
-          pw[j] = of[j] == 0 ? 1.0 : (of[j] == 1 ? cf[j] : (of[j] == 2 ? cf2 : cf2 * cf[j]));
-          pr[j] = orr[j] == 0 ? 1.0 : (orr[j] == 1 ? cr[j] : (orr[j] == 2 ? cr2 : cr2 * cr[j]));
-          sumg = sumg - of[j] * gf[j];
-          sumg = sumg + orr[j] * gr[j];
-          if (JAC) {
-            sumh = sumh - of[j] * hf[j];
-            sumh = sumh + orr[j] * hr[j];
-          }
-        }
-        Pf = pw[0] * pw[1] * pw[2];
-        Pr = pr[0] * pr[1] * pr[2];
-      }
-      // kr = kf / Kc with Kc = exp(-sum nu g/RT) (p_atm/RT)^(sum nu)
-      const double kr = rev ? exp(lnkf + sumg + dnu * lnRTp) : 0.0;
-      const double q0 = kf * Pf - kr * Pr;
-      double theta = 1.0, beta = 0.0, dthdT = 0.0;
-      const double dlnkf = (bb + ear * rT) * rT;
-      if (type >= 1) {
-        double M = Ctot;
-        const int eoff = w.w & 0xffff, neff = (w.w >> 16) & 0xff;
-        for (int e = 0; e < neff; ++e) M = M + L.eff_am1[eoff + e] * ca.C[L.eff_sp[eoff + e]];
-        if (type == 1) {
-          theta = M;
-          beta = 1.0;
-        } else {
-          const double* tr = L.troe + 8 * ((w.w >> 24) & 0xff);
-          const double k0 = exp(tr[0] + tr[1] * lnT - tr[2] * rT);
-          const double dlnk0 = (tr[1] + tr[2] * rT) * rT;
-          double Prd = k0 * M / kf;
-          if (Prd < 1e-300) Prd = 1e-300;
-          const double ta = tr[3];
-          const double e3 = exp(-T * tr[4]), e1 = exp(-T * tr[5]);
-          double Fc = (1.0 - ta) * e3 + ta * e1;
-          double dFc = -(1.0 - ta) * tr[4] * e3 - ta * tr[5] * e1;
-          if (tr[7] != 0.0) {
-            const double e2 = exp(-tr[6] * rT);
-            Fc = Fc + e2;
-            dFc = dFc + tr[6] * rT * rT * e2;
-          }
-          if (Fc < 1e-300) Fc = 1e-300;
-          const double Lc = log10(Fc);
-          const double c = -0.4 - 0.67 * Lc;
-          const double N = 0.75 - 1.27 * Lc;
-          const double X = log10(Prd) + c;
-          const double den = N - 0.14 * X;
-          const double f1 = X / den;
-          const double opf = 1.0 + f1 * f1;
-          const double lgF = Lc / opf;
-          const double F = exp(lgF * kLn10);
-          const double lind = Prd / (1.0 + Prd);
-          theta = lind * F;
-          if (JAC) {
-            const double dlogF_dX = -Lc * 2.0 * f1 / (opf * opf) * (N / (den * den));
-            const double dlogF_dPr = dlogF_dX / (Prd * kLn10);
-            const double dPhi = F / ((1.0 + Prd) * (1.0 + Prd)) + lind * F * kLn10 * dlogF_dPr;
-            beta = dPhi * k0 / kf;
-            const double dPr_dT = Prd * (dlnk0 - dlnkf);
-            const double dL_dT = dFc / (Fc * kLn10);
-            const double df1_dL = (-0.67 * den - X * (-1.27 + 0.14 * 0.67)) / (den * den);
-            const double dlogF_dL = 1.0 / opf - Lc * 2.0 * f1 * df1_dL / (opf * opf);
-            dthdT = dPhi * dPr_dT + lind * (F * kLn10 * dlogF_dL * dL_dT);
-          }
-        }
-      }
-      ca.RB[rx] = theta * q0;
-      if (JAC) {
-        const double dlnkr = rev ? dlnkf - (sumh * rT - dnu * rT) : 0.0;
-        ca.RB[nr + rx] = kf * theta;
-        ca.RB[2 * nr + rx] = kr * theta;
-        ca.RB[3 * nr + rx] = q0 * beta;
-        ca.RB[4 * nr + rx] = theta * (kf * dlnkf * Pf - kr * dlnkr * Pr) + q0 * dthdT;
-      }
+      reaction_rate<JAC>(L, ca.C, ca.gRT, ca.hRT, ca.RB, nr, rx, T, rT, lnT, lnRTp, Ctot);
     }
     wsync();
 

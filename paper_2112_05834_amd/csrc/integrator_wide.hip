@@ -1,0 +1,744 @@
+// Per-cell stiff chemistry integration for mechanisms too large for one
+// wave (n = Ns + 1 up to 256): one workgroup of 256 threads per cell.
+//
+// The Jacobian J and the Rosenbrock matrix M = I/(gamma h) - J of a
+// 160-species cell are 161 x 161 FP64 (207 KB each): they fit neither one
+// wave's registers nor the 160 KB LDS of a CU. Each resident workgroup
+// therefore owns a workspace slot in HBM holding J and M (column-major,
+// leading dimension ld); the number of slots, and so of cells in flight, is
+// bounded by the HBM budget. Everything else of the cell (state, stage
+// vectors, concentrations, per-reaction rates) lives in LDS.
+//
+// The LU is a right-looking blocked getrf: a panel of 16 columns is factored
+// in LDS with partial pivoting (first index of the largest |a|), its row
+// interchanges are applied to the other columns, the 16-row block of U is
+// solved against the unit-lower diagonal block, and the trailing matrix
+// receives the rank-16 update in one pass through HBM. Every element sees
+// the same sequence of operations as in an unblocked row-swapping LU, in the
+// same order, so the factors do not depend on the blocking.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace chemk {
+
+namespace {
+
+using namespace dev;
+
+constexpr int kT = kWideThreads;
+constexpr int kNB = kWidePanel;
+
+// Per-cell LDS area. Region A (right-hand-side buffers) and region B (LU
+// panel and U block) are never live at the same time and share storage.
+struct Wide {
+  double *C, *gRT, *hRT, *RB;                   // A: ns, ns, ns, 5 nr
+  double *panel, *U12;                          // B: kNB ld, kNB ld
+  double *y, *f0, *fs, *ys, *yn, *v, *u[4];     // ld each
+  double* red;                                  // 16
+  int* piv;                                     // ld
+  int* perm;                                    // ld
+  int* ired;                                    // 16
+  unsigned long long* qslot;                    // 1
+};
+
+__host__ __device__ inline int wide_region(int ns, int nr, int ld) {
+  const int a = 3 * ns + 5 * nr;
+  const int b = 2 * kNB * ld;
+  return ((a > b ? a : b) + 1) & ~1;
+}
+
+// doubles: region, 10 vectors, reduction scratch; ints: piv, perm, ired;
+// one 64-bit queue slot
+__host__ __device__ inline int wide_doubles(int ns, int nr, int ld) {
+  return wide_region(ns, nr, ld) + 10 * ld + 16 + (2 * ld + 16) / 2 + 2;
+}
+
+__device__ inline Wide wide_area(double* base, int ns, int nr, int ld) {
+  Wide W;
+  W.C = base;
+  W.gRT = W.C + ns;
+  W.hRT = W.gRT + ns;
+  W.RB = W.hRT + ns;
+  W.panel = base;
+  W.U12 = base + kNB * ld;
+  double* q = base + wide_region(ns, nr, ld);
+  W.y = q;
+  W.f0 = q + ld;
+  W.fs = q + 2 * ld;
+  W.ys = q + 3 * ld;
+  W.yn = q + 4 * ld;
+  W.v = q + 5 * ld;
+  for (int k = 0; k < 4; ++k) W.u[k] = q + (6 + k) * ld;
+  W.red = q + 10 * ld;
+  int* ip = reinterpret_cast<int*>(W.red + 16);
+  W.piv = ip;
+  W.perm = ip + ld;
+  W.ired = ip + 2 * ld;
+  W.qslot = reinterpret_cast<unsigned long long*>(ip + 2 * ld + 16);
+  return W;
+}
+
+// ---- workgroup reductions (fixed pairing: butterfly in the wave, then
+// waves (0+1)+(2+3)); every thread receives the same value ----
+__device__ __forceinline__ double bsum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// index of the largest key, lowest index among equal keys
+__device__ __forceinline__ int bargmax(double key, int idx, double* red, int* ired) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double ok = __shfl_xor(key, off);
+    const int oi = __shfl_xor(idx, off);
+    if (ok > key || (ok == key && oi < idx)) {
+      key = ok;
+      idx = oi;
+    }
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[8 + (threadIdx.x >> 6)] = key;
+    ired[threadIdx.x >> 6] = idx;
+  }
+  __syncthreads();
+  double bk = red[8];
+  int bi = ired[0];
+  for (int w = 1; w < 4; ++w) {
+    const double k2 = red[8 + w];
+    const int i2 = ired[w];
+    if (k2 > bk || (k2 == bk && i2 < bi)) {
+      bk = k2;
+      bi = i2;
+    }
+  }
+  return bi;
+}
+
+// ---- right-hand side and analytical Jacobian ----------------------------------
+// f = dy/dt at y (LDS vector); with JAC also J = df/dy, column-major in HBM:
+// element (i, j) at J[j * ld + i]. Thread t owns state component t (0 = T,
+// t = 1..Ns species t-1) and, for the Jacobian, row t.
+template <bool JAC>
+__device__ void rhs_w(const MechArgs& A, const MechLds& L, const Wide& W, double p, const double* yv, double* fout,
+                      double* J, int ld) {
+  const int ns = A.ns, nr = A.nr, n = ns + 1;
+  const int t = threadIdx.x;
+  const bool sp = t >= 1 && t <= ns;
+  const int s = sp ? t - 1 : 0;
+  const double T = yv[0];
+  const double rT = 1.0 / T;
+  const double lnT = log(T);
+  const double Ys = sp ? yv[t] : 0.0;
+  const double rWs = sp ? L.rW[s] : 0.0;
+  const double invWbar = bsum(Ys * rWs, W.red);
+  const double Wbar = 1.0 / invWbar;
+  const double rho = p * Wbar / (kR * T);
+  const double Cs = rho * Ys * rWs;
+  if (sp) W.C[s] = Cs;
+  const double Ctot = bsum(Cs, W.red);
+  double cpR = 0.0, hRT = 0.0, dcpR = 0.0;
+  if (sp) {
+    double gRT;
+    nasa7<JAC>(A.nasa + 16 * s, T, rT, lnT, cpR, hRT, gRT, dcpR);
+    W.gRT[s] = gRT;
+    W.hRT[s] = hRT;
+  }
+  const double cp = bsum(Ys * cpR * kR * rWs, W.red);
+  double dcp = 0.0;
+  if (JAC) {
+    dcp = bsum(Ys * dcpR * kR * rWs, W.red);
+    for (int e = t; e < n * ld; e += kT) J[e] = 0.0;
+  }
+  __syncthreads();
+  const double lnRTp = log(kR * T / kPatm);
+  for (int rx = t; rx < nr; rx += kT) reaction_rate<JAC>(L, W.C, W.gRT, W.hRT, W.RB, nr, rx, T, rT, lnT, lnRTp, Ctot);
+  __syncthreads();
+
+  // species: production rates and, with JAC, the rows d(omega)/dC (thread t
+  // alone updates row t, in entry order)
+  double om = 0.0, wT = 0.0, td = 0.0;
+  if (sp) {
+    const int e0 = L.sp_off[s], e1 = L.sp_off[s + 1];
+    if (!JAC) {
+      for (int e = e0; e < e1; ++e) {
+        const unsigned ent = L.sp_ent[e];
+        const double nu = static_cast<double>(static_cast<int>(ent >> 12) - 8);
+        om = om + nu * W.RB[ent & 0xfff];
+      }
+    } else {
+      double* Jr = J + t;
+      for (int e = e0; e < e1; ++e) {
+        const unsigned ent = L.sp_ent[e];
+        const int rx = ent & 0xfff;
+        const double nu = static_cast<double>(static_cast<int>(ent >> 12) - 8);
+        const uint4 wc = L.rint[rx];
+        const double qr = W.RB[rx], kfT = W.RB[nr + rx], krT = W.RB[2 * nr + rx];
+        const double q0b = W.RB[3 * nr + rx], dqdT = W.RB[4 * nr + rx];
+        const int nre = (wc.x >> 24) & 0xf, npr = (wc.y >> 24) & 0xf;
+        double Pf, Pr, dPf[3], dPr[3];
+        int sf[3], sr[3];
+        mass_action(W.C, wc.x, wc.z, nre, Pf, dPf, sf);
+        mass_action(W.C, wc.y, wc.z >> 12, npr, Pr, dPr, sr);
+        om = om + nu * qr;
+        wT = wT + nu * dqdT;
+        const double af = nu * kfT, ar = nu * krT;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          if (j < nre) Jr[(1 + sf[j]) * ld] += af * dPf[j];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          if (j < npr) Jr[(1 + sr[j]) * ld] += -(ar * dPr[j]);
+        const int type = (wc.x >> 28) & 3;
+        if (type >= 1) {
+          const double ab = nu * q0b;
+          td = td + ab;
+          const int eoff = wc.w & 0xffff, neff = (wc.w >> 16) & 0xff;
+          for (int q = 0; q < neff; ++q) Jr[(1 + L.eff_sp[eoff + q]) * ld] += ab * L.eff_am1[eoff + q];
+        }
+      }
+    }
+  }
+  const double fY = sp ? A.W[s] * om / rho : 0.0;
+  const double Q = bsum(hRT * kR * T * om, W.red);
+  const double rcp = rho * cp;
+  const double fT = -Q / rcp;
+  if (t < n) fout[t] = (t == 0) ? fT : fY;
+  if (!JAC) {
+    __syncthreads();
+    return;
+  }
+
+  // chain rule from d(omega)/dC and d(omega)/dT to y = (T, Y)
+  __syncthreads();
+  double sv = 0.0;
+  if (sp) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int k = 0;
+    for (; k + 3 < ns; k += 4) {
+      a0 = fma(J[(1 + k) * ld + t], W.C[k], a0);
+      a1 = fma(J[(2 + k) * ld + t], W.C[k + 1], a1);
+      a2 = fma(J[(3 + k) * ld + t], W.C[k + 2], a2);
+      a3 = fma(J[(4 + k) * ld + t], W.C[k + 3], a3);
+    }
+    if (k < ns) a0 = fma(J[(1 + k) * ld + t], W.C[k], a0);
+    if (k + 1 < ns) a1 = fma(J[(2 + k) * ld + t], W.C[k + 1], a1);
+    if (k + 2 < ns) a2 = fma(J[(3 + k) * ld + t], W.C[k + 2], a2);
+    sv = ((a0 + a1) + (a2 + a3)) + td * Ctot;
+  }
+  const double HS = bsum(hRT * sv, W.red);
+  const double HT = bsum(hRT * td, W.red);
+  const double dQdT = bsum(sp ? cpR * kR * om + hRT * kR * T * (wT - sv / T) : 0.0, W.red);
+  double JT = 0.0;
+  if (sp) {
+    const double* col = J + t * ld + 1;    // column t, rows 1..ns
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+    int q = 0;
+    for (; q + 3 < ns; q += 4) {
+      c0 = fma(W.hRT[q], col[q], c0);
+      c1 = fma(W.hRT[q + 1], col[q + 1], c1);
+      c2 = fma(W.hRT[q + 2], col[q + 2], c2);
+      c3 = fma(W.hRT[q + 3], col[q + 3], c3);
+    }
+    if (q < ns) c0 = fma(W.hRT[q], col[q], c0);
+    if (q + 1 < ns) c1 = fma(W.hRT[q + 1], col[q + 1], c1);
+    if (q + 2 < ns) c2 = fma(W.hRT[q + 2], col[q + 2], c2);
+    const double cs = (c0 + c1) + (c2 + c3);
+    const double dQdY = kR * T * ((rho * rWs) * (cs + HT) - (Wbar * rWs) * HS);
+    const double drcp = rho * cpR * kR * rWs - rcp * Wbar * rWs;
+    JT = -(dQdY + fT * drcp) / rcp;
+  }
+  __syncthreads();
+  if (sp) {
+    const double Wi_rho = A.W[s] / rho;
+    for (int k = 0; k < ns; ++k) {
+      const double rWk = L.rW[k];
+      const double D = J[(1 + k) * ld + t] + td;
+      const double dw = (rho * rWk) * D - (Wbar * rWk) * sv;
+      J[(1 + k) * ld + t] = Wi_rho * dw + fY * Wbar * rWk;
+    }
+    J[t] = Wi_rho * (wT - sv / T) + fY / T;   // (t, 0)
+    J[t * ld] = JT;                           // (0, t)
+  } else if (t == 0) {
+    const double drcp = -rcp / T + rho * dcp;
+    J[0] = -(dQdT + fT * drcp) / rcp;
+  }
+  __syncthreads();
+}
+
+// ---- blocked LU with partial pivoting ---------------------------------------------
+// M: n x n column-major (leading dimension ld) in HBM, overwritten by L (unit
+// lower, below the diagonal) and U. W.piv[k] = row interchanged with row k
+// at step k, W.perm = the resulting row order. Returns the first zero pivot
+// column + 1 (0 if none); such a column is left unreduced, as getrf does.
+__device__ int lu_w(double* M, int n, int ld, const Wide& W) {
+  const int t = threadIdx.x;
+  for (int i = t; i < ld; i += kT) W.perm[i] = i;
+  int info = 0;
+  for (int k0 = 0; k0 < n; k0 += kNB) {
+    const int nb = min(kNB, n - k0);
+    for (int e = t; e < nb * ld; e += kT) {
+      const int c = e / ld, r = e - c * ld;
+      W.panel[e] = (r >= k0 && r < n) ? M[(k0 + c) * ld + r] : 0.0;
+    }
+    __syncthreads();
+    for (int c = 0; c < nb; ++c) {
+      const int k = k0 + c;
+      double* pc = W.panel + c * ld;
+      double key = -1.0;
+      int idx = 1 << 30;
+      if (t >= k && t < n) {
+        const double av = fabs(pc[t]);
+        // a NaN on the diagonal stays the pivot; elsewhere it never wins
+        key = (av != av) ? (t == k ? INFINITY : -1.0) : av;
+        idx = t;
+      }
+      const int pv = bargmax(key, idx, W.red, W.ired);
+      if (t == 0) {
+        W.piv[k] = pv;
+        const int tmp = W.perm[k];
+        W.perm[k] = W.perm[pv];
+        W.perm[pv] = tmp;
+      }
+      if (pv != k && t < nb) {
+        double* q = W.panel + t * ld;
+        const double tmp = q[k];
+        q[k] = q[pv];
+        q[pv] = tmp;
+      }
+      __syncthreads();
+      const double akk = pc[k];
+      if (akk == 0.0) {
+        if (!info) info = k + 1;
+        continue;
+      }
+      if (t > k && t < n) {
+        const double l = pc[t] / akk;
+        pc[t] = l;
+        for (int c2 = c + 1; c2 < nb; ++c2) {
+          double* q = W.panel + c2 * ld;
+          q[t] = q[t] - l * q[k];
+        }
+      }
+      __syncthreads();
+    }
+    // panel back to HBM, and its interchanges on the other columns
+    for (int e = t; e < nb * ld; e += kT) {
+      const int c = e / ld, r = e - c * ld;
+      if (r >= k0 && r < n) M[(k0 + c) * ld + r] = W.panel[e];
+    }
+    for (int j = t; j < n; j += kT) {
+      if (j >= k0 && j < k0 + nb) continue;
+      double* col = M + j * ld;
+      for (int c = 0; c < nb; ++c) {
+        const int k = k0 + c, pv = W.piv[k];
+        if (pv != k) {
+          const double tmp = col[k];
+          col[k] = col[pv];
+          col[pv] = tmp;
+        }
+      }
+    }
+    __syncthreads();
+    const int j0 = k0 + nb, m = n - j0;
+    if (m > 0) {
+      // U block: L11^-1 A12, one column per thread
+      for (int j = j0 + t; j < n; j += kT) {
+        double* col = M + j * ld;
+        double x[kNB];
+#pragma unroll
+        for (int q = 0; q < kNB; ++q) x[q] = q < nb ? col[k0 + q] : 0.0;
+#pragma unroll
+        for (int q = 1; q < kNB; ++q) {
+#pragma unroll
+          for (int q2 = 0; q2 < q; ++q2)
+            if (q < nb) x[q] = x[q] - W.panel[q2 * ld + k0 + q] * x[q2];
+        }
+#pragma unroll
+        for (int q = 0; q < kNB; ++q) {
+          if (q < nb) {
+            col[k0 + q] = x[q];
+            W.U12[(j - j0) * kNB + q] = x[q];
+          }
+        }
+      }
+      __syncthreads();
+      // trailing update A22 -= L21 U12, rows fastest (coalesced)
+      const long long mm = static_cast<long long>(m) * m;
+      for (long long e = t; e < mm; e += kT) {
+        const int jj = static_cast<int>(e / m);
+        const int r = j0 + static_cast<int>(e - static_cast<long long>(jj) * m);
+        const int j = j0 + jj;
+        double av = M[j * ld + r];
+        const double* u = W.U12 + jj * kNB;
+        for (int q = 0; q < nb; ++q) av = av - W.panel[q * ld + r] * u[q];
+        M[j * ld + r] = av;
+      }
+      __syncthreads();
+    }
+  }
+  return info;
+}
+
+// x = M^-1 b with the factors of lu_w (b, x: LDS vectors, distinct).
+// Forward substitution in column blocks (each element receives its terms in
+// ascending column order), then backward in column blocks from the bottom.
+__device__ void solve_w(const double* M, int n, int ld, const Wide& W, const double* b, double* x) {
+  const int t = threadIdx.x;
+  if (t < n) x[t] = b[W.perm[t]];
+  __syncthreads();
+  for (int k0 = 0; k0 < n; k0 += kNB) {
+    const int nb = min(kNB, n - k0);
+    if (t < 64) {
+      double xv = t < nb ? x[k0 + t] : 0.0;
+      for (int q = 0; q + 1 < nb; ++q) {
+        const double z = __shfl(xv, q);
+        if (t > q && t < nb) xv = xv - M[(k0 + q) * ld + k0 + t] * z;
+      }
+      if (t < nb) x[k0 + t] = xv;
+    }
+    __syncthreads();
+    for (int r = k0 + nb + t; r < n; r += kT) {
+      double a = x[r];
+      for (int q = 0; q < nb; ++q) a = a - M[(k0 + q) * ld + r] * x[k0 + q];
+      x[r] = a;
+    }
+    __syncthreads();
+  }
+  for (int k0 = ((n - 1) / kNB) * kNB; k0 >= 0; k0 -= kNB) {
+    const int nb = min(kNB, n - k0);
+    if (t < 64) {
+      double xv = t < nb ? x[k0 + t] : 0.0;
+      for (int q = nb - 1; q >= 0; --q) {
+        const double d = (t == q) ? xv / M[(k0 + q) * ld + k0 + q] : 0.0;
+        const double z = __shfl(d, q);
+        if (t == q) {
+          xv = z;
+        } else if (t < q) {
+          xv = xv - M[(k0 + q) * ld + k0 + t] * z;
+        }
+      }
+      if (t < nb) x[k0 + t] = xv;
+    }
+    __syncthreads();
+    for (int r = t; r < k0; r += kT) {
+      double a = x[r];
+      for (int q = 0; q < nb; ++q) a = a - M[(k0 + q) * ld + r] * x[k0 + q];
+      x[r] = a;
+    }
+    __syncthreads();
+  }
+}
+
+// ---- adaptive Rodas3 over [0, dt] for one cell (state in W.y) ---------------------
+__device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, double* J, double* M, int ld,
+                            const OptsDev& o, double p, double dt, double& hio, int& nacc_o, int& nrej_o,
+                            int& status_o) {
+  const int n = A.ns + 1;
+  const int t = threadIdx.x;
+  int status = 0;
+  const bool bad = (t < n && !isfinite(W.y[t])) || !isfinite(p);
+  if (__syncthreads_or(bad)) status = 3;
+  double h = hio > 0.0 ? hio : dt;
+  double hnext = h, tt = 0.0;
+  int nacc = 0, nrej = 0, att = 0, consec = 0;
+  bool need = true;
+  while (status == 0 && tt < dt) {
+    if (att >= o.max_steps) {
+      status = 1;
+      break;
+    }
+    if (need) {
+      rhs_w<true>(A, L, W, p, W.y, W.f0, J, ld);
+      need = false;
+    }
+    const double rem = dt - tt;
+    double hc = h;
+    bool clipped = false;
+    if (hc >= rem) {
+      hc = rem;
+      clipped = true;
+    }
+    if (hc < kHMin) {
+      status = 2;
+      break;
+    }
+    const double g = 1.0 / (kGamma * hc);
+    for (int e = t; e < n * ld; e += kT) {
+      const int c = e / ld, r = e - c * ld;
+      M[e] = (r == c ? g : 0.0) - J[e];
+    }
+    __syncthreads();
+    const int info = lu_w(M, n, ld, W);
+    ++att;
+    if (info) {
+      status = 4;
+      break;
+    }
+    for (int st = 0; st < 4; ++st) {
+      if (st >= 2) {
+        const bool s3 = st == 2;
+        if (t < n) {
+          double ys = W.y[t] + (s3 ? kA31 : kA41) * W.u[0][t];
+          ys = ys + 0.0 * W.u[1][t];
+          if (!s3) ys = ys + kA43 * W.u[2][t];
+          W.ys[t] = ys;
+        }
+        __syncthreads();
+        rhs_w<false>(A, L, W, p, W.ys, W.fs, nullptr, ld);
+      }
+      if (t < n) {
+        double v;
+        if (st == 0) {
+          v = W.f0[t];
+        } else if (st == 1) {
+          v = W.f0[t] + (kC21 / hc) * W.u[0][t];
+        } else {
+          const bool s3 = st == 2;
+          v = W.fs[t] + ((s3 ? kC31 : kC41) / hc) * W.u[0][t];
+          v = v + ((s3 ? kC32 : kC42) / hc) * W.u[1][t];
+          if (!s3) v = v + (kC43 / hc) * W.u[2][t];
+        }
+        W.v[t] = v;
+      }
+      __syncthreads();
+      solve_w(M, n, ld, W, W.v, W.u[st]);
+    }
+    double yn = 0.0, q = 0.0;
+    if (t < n) {
+      yn = W.y[t] + 2.0 * W.u[0][t];
+      yn = yn + 0.0 * W.u[1][t];
+      yn = yn + 1.0 * W.u[2][t];
+      yn = yn + 1.0 * W.u[3][t];
+      const double sc = o.atol + o.rtol * fmax(fabs(W.y[t]), fabs(yn));
+      q = W.u[3][t] / sc;
+      W.yn[t] = yn;
+    }
+    const double acc = bsum(t < n ? q * q : 0.0, W.red);
+    double err = sqrt(acc / n);
+    const bool nonfinite = __syncthreads_or(t < n && !isfinite(yn));
+    double hnew;
+    if (nonfinite || !isfinite(err)) {
+      err = INFINITY;
+      hnew = hc * kFacRej;
+    } else {
+      double fac = kFacSafe / cbrt(fmax(err, 1e-10));
+      fac = fmin(kFacMax, fmax(kFacMin, fac));
+      hnew = hc * fac;
+    }
+    if (err <= 1.0) {
+      if (consec > 0) hnew = fmin(hnew, hc);
+      const double Tn = W.yn[0];
+      if (!(Tn >= kTMin && Tn <= kTMax)) {
+        status = 5;
+        break;
+      }
+      if (t < n) W.y[t] = W.yn[t];
+      ++nacc;
+      tt = clipped ? dt : tt + hc;
+      hnext = clipped ? fmax(hnew, h) : hnew;
+      h = hnew;
+      consec = 0;
+      need = true;
+      __syncthreads();
+    } else {
+      ++nrej;
+      ++consec;
+      if (consec >= 2) hnew = hc * kFacRej;
+      h = hnew;
+    }
+  }
+  if (status != 0) hnext = h;
+  hio = hnext;
+  nacc_o = nacc;
+  nrej_o = nrej;
+  status_o = status;
+}
+
+__device__ void run_cell_w(const IntegrateArgs& a, const MechLds& L, const Wide& W, double* J, double* M,
+                           long long cell) {
+  const int ns = a.m.ns, n = ns + 1, w2 = ns + 2;
+  const int t = threadIdx.x;
+  const double* pin = a.phi_in + cell * w2;
+  const double p = pin[1];
+  if (t < n) W.y[t] = t == 0 ? pin[0] : pin[1 + t];
+  __syncthreads();
+  float ft[4] = {0.f, 0.f, 0.f, 0.f};
+  if (a.log.cap > 0) {
+    const double lv = (t >= 1 && t <= ns) ? log10(fmax(W.y[t], 1e-30)) : 0.0;
+    const double ell = bsum(lv, W.red) / ns;
+    ft[0] = static_cast<float>((W.y[0] - 1500.0) / 700.0);
+    ft[1] = static_cast<float>(log(p / 1e5));
+    ft[2] = static_cast<float>(ell / 10.0);
+    ft[3] = static_cast<float>(log10(a.dt / 1e-6));
+  }
+  double h = a.h_io ? a.h_io[cell] : 0.0;
+  int nacc, nrej, st;
+  integrate_w(a.m, L, W, J, M, a.ld, a.o, p, a.dt, h, nacc, nrej, st);
+  double* pout = a.phi_out + cell * w2;
+  if (t < n) pout[t == 0 ? 0 : 1 + t] = W.y[t];
+  if (t == 0) {
+    pout[1] = p;
+    if (a.h_io) a.h_io[cell] = h;
+    if (a.accumulate) {
+      if (a.n_acc) a.n_acc[cell] += nacc;
+      if (a.n_rej) a.n_rej[cell] += nrej;
+      if (a.status && a.status[cell] == 0) a.status[cell] = static_cast<signed char>(st);
+    } else {
+      if (a.n_acc) a.n_acc[cell] = nacc;
+      if (a.n_rej) a.n_rej[cell] = nrej;
+      if (a.status) a.status[cell] = static_cast<signed char>(st);
+    }
+    if (a.log.cap > 0) {
+      const unsigned long long k = atomicAdd(a.log.head, 1ull) % static_cast<unsigned long long>(a.log.cap);
+      for (int c = 0; c < 4; ++c) a.log.feats[4 * k + c] = ft[c];
+      a.log.target[k] = logf(static_cast<float>(nacc + nrej > 0 ? nacc + nrej : 1));
+    }
+  }
+  __syncthreads();
+}
+
+// ---- kernels ---------------------------------------------------------------------
+// Each workgroup owns workspace slot blockIdx.x. Plain: cells blockIdx.x,
+// blockIdx.x + gridDim.x, ... (static); persistent: chunks from the queue.
+template <bool PERSIST>
+__global__ void __launch_bounds__(256) k_integrate_wide(IntegrateArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  stage_mech(smem, a.m);
+  const MechLds L = mech_views(smem, a.m);
+  const Wide W = wide_area(reinterpret_cast<double*>(smem + a.m.lds_bytes), a.m.ns, a.m.nr, a.ld);
+  double* J = a.ws + static_cast<long long>(blockIdx.x) * a.ws_stride;
+  double* M = J + static_cast<long long>(a.m.ns + 1) * a.ld;
+  if (!PERSIST) {
+    for (long long cell = blockIdx.x; cell < a.n; cell += gridDim.x) run_cell_w(a, L, W, J, M, cell);
+  } else {
+    for (;;) {
+      if (threadIdx.x == 0) W.qslot[0] = atomicAdd(a.head, static_cast<unsigned long long>(a.chunk));
+      __syncthreads();
+      const unsigned long long idx = W.qslot[0];
+      __syncthreads();
+      if (idx >= static_cast<unsigned long long>(a.n)) break;
+      const long long end = min(static_cast<long long>(idx) + a.chunk, a.n);
+      for (long long q = static_cast<long long>(idx); q < end; ++q) {
+        const long long cell = a.perm ? static_cast<long long>(a.perm[q]) : q;
+        run_cell_w(a, L, W, J, M, cell);
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_eval_wide(EvalArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  stage_mech(smem, a.m);
+  const MechLds L = mech_views(smem, a.m);
+  const Wide W = wide_area(reinterpret_cast<double*>(smem + a.m.lds_bytes), a.m.ns, a.m.nr, a.ld);
+  double* J = a.ws + static_cast<long long>(blockIdx.x) * a.ws_stride;
+  const int ns = a.m.ns, n = ns + 1, ld = a.ld;
+  const int t = threadIdx.x;
+  for (long long cell = blockIdx.x; cell < a.n; cell += gridDim.x) {
+    const double* pin = a.phi + cell * (ns + 2);
+    const double p = pin[1];
+    if (t < n) W.y[t] = t == 0 ? pin[0] : pin[1 + t];
+    __syncthreads();
+    if (a.J) {
+      rhs_w<true>(a.m, L, W, p, W.y, W.f0, J, ld);
+    } else {
+      rhs_w<false>(a.m, L, W, p, W.y, W.f0, nullptr, ld);
+    }
+    if (t < n) a.f[cell * n + t] = W.f0[t];
+    if (a.J) {
+      const long long nn = static_cast<long long>(n) * n;
+      for (long long e = t; e < nn; e += kT) {
+        const int i = static_cast<int>(e / n), j = static_cast<int>(e - static_cast<long long>(i) * n);
+        a.J[cell * nn + e] = J[j * ld + i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_lu_wide(LuArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = a.n, ld = a.ld;
+  const Wide W = wide_area(reinterpret_cast<double*>(smem), 0, 0, ld);
+  double* M = a.ws + static_cast<long long>(blockIdx.x) * a.ws_stride;
+  const int t = threadIdx.x;
+  const long long nn = static_cast<long long>(n) * n;
+  for (long long m = blockIdx.x; m < a.batch; m += gridDim.x) {
+    for (long long e = t; e < nn; e += kT) {
+      const int i = static_cast<int>(e / n), j = static_cast<int>(e - static_cast<long long>(i) * n);
+      M[j * ld + i] = a.A[m * nn + e];
+    }
+    __syncthreads();
+    const int info = lu_w(M, n, ld, W);
+    for (long long e = t; e < nn; e += kT) {
+      const int i = static_cast<int>(e / n), j = static_cast<int>(e - static_cast<long long>(i) * n);
+      a.A[m * nn + e] = M[j * ld + i];
+    }
+    if (t < n) a.piv[m * n + t] = W.piv[t];
+    if (t == 0) a.info[m] = info;
+    if (a.b) {
+      if (t < n) W.v[t] = a.b[m * n + t];
+      __syncthreads();
+      solve_w(M, n, ld, W, W.v, W.u[0]);
+      if (t < n) a.b[m * n + t] = W.u[0][t];
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+int wide_cell_bytes(int ns, int nr, int ld) { return static_cast<int>(sizeof(double)) * wide_doubles(ns, nr, ld); }
+
+template <bool P>
+static void* wide_fn() {
+  return reinterpret_cast<void*>(&k_integrate_wide<P>);
+}
+
+hipError_t launch_integrate_wide(bool persistent, int grid, const IntegrateArgs& a, size_t lds_bytes,
+                                 hipStream_t st) {
+  void* fn = persistent ? wide_fn<true>() : wide_fn<false>();
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
+  if (e != hipSuccess) return e;
+  IntegrateArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchKernel(fn, dim3(grid), dim3(kT), args, lds_bytes, st);
+}
+
+int integrate_wide_blocks_per_cu(bool persistent, size_t lds_bytes) {
+  void* fn = persistent ? wide_fn<true>() : wide_fn<false>();
+  hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kT, lds_bytes) != hipSuccess) return 0;
+  return nb;
+}
+
+hipError_t launch_eval_wide(int grid, const EvalArgs& a, size_t lds_bytes, hipStream_t st) {
+  void* fn = reinterpret_cast<void*>(&k_eval_wide);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
+  if (e != hipSuccess) return e;
+  EvalArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchKernel(fn, dim3(grid), dim3(kT), args, lds_bytes, st);
+}
+
+hipError_t launch_lu_wide(int grid, const LuArgs& a, size_t lds_bytes, hipStream_t st) {
+  void* fn = reinterpret_cast<void*>(&k_lu_wide);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
+  if (e != hipSuccess) return e;
+  LuArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchKernel(fn, dim3(grid), dim3(kT), args, lds_bytes, st);
+}
+
+}  // namespace chemk

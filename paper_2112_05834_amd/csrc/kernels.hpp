@@ -50,6 +50,11 @@ struct IntegrateArgs {
   unsigned long long* head;     // queue head (persistent)
   int chunk;                    // cells per queue pull
   LogArgs log;
+  // workgroup-per-cell kernel: per-slot workspace in HBM (J and M, n x ld
+  // column-major each), one slot per resident workgroup
+  double* ws;
+  long long ws_stride;          // doubles per slot
+  int ld;                       // leading dimension of J and M
 };
 
 struct EvalArgs {
@@ -60,6 +65,9 @@ struct EvalArgs {
   double* J;
   int cell_doubles;
   int wpb;
+  double* ws;
+  long long ws_stride;
+  int ld;
 };
 
 struct LuArgs {
@@ -70,13 +78,27 @@ struct LuArgs {
   int* info;
   double* b;
   int wpb;
+  double* ws;
+  long long ws_stride;
+  int ld;
 };
 
-// Kernel variant: state size NN (compiled), lanes per cell G.
+// Kernel variant: state size NN (compiled), lanes per cell G. The
+// workgroup-per-cell kernel for larger mechanisms is {kWideNN, 256}.
 struct Variant {
   int nn;
   int g;
 };
+constexpr int kWideNN = 256;          // largest n of the workgroup kernel
+constexpr int kWideThreads = 256;     // threads per cell
+constexpr int kWidePanel = 16;        // LU panel width
+inline int wide_ld(int n) { return (n + 15) & ~15; }
+// LDS bytes of the workgroup kernel's per-cell area (after the mechanism prefix)
+int wide_cell_bytes(int ns, int nr, int ld);
+hipError_t launch_integrate_wide(bool persistent, int grid, const IntegrateArgs& a, size_t lds_bytes, hipStream_t st);
+hipError_t launch_eval_wide(int grid, const EvalArgs& a, size_t lds_bytes, hipStream_t st);
+hipError_t launch_lu_wide(int grid, const LuArgs& a, size_t lds_bytes, hipStream_t st);
+int integrate_wide_blocks_per_cu(bool persistent, size_t lds_bytes);
 
 // Which compiled variants exist for a state size n (returns count, fills out).
 int variants_for(int n, Variant* out, int max_out);

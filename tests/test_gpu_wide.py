@@ -1,0 +1,191 @@
+"""The workgroup-per-cell path (160 species, 800 reactions: n = 161) on the
+GPU through the C ABI, against the CPU oracle.
+
+* right-hand side and analytical Jacobian: rel 1e-9 (summation order only);
+* blocked LU: pivots identical, factors bit-identical to the oracle's
+  unblocked LU (every element sees the same operations in the same order);
+  solves rel 1e-10;
+* integration: Y rel 1e-6 / abs 1e-10, T rel 1e-8 on cells with the oracle's
+  step sequence, at most 0.1% of cells on another sequence;
+* schedules (plain, persistent, binned, small chunk) and an HBM budget of a
+  few workspace slots give bit-identical results.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2112_05834_amd import chem, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+NCPU = max(1, min(16, os.cpu_count() or 1))
+
+
+def _to(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def large(tmp_path_factory):
+    d = str(tmp_path_factory.mktemp("large"))
+    wl, mech, path, phi = synth.workload_inputs("large160_524288", d, 4096)
+    return wl, mech, path, phi
+
+
+def _scaled(J, y):
+    s = np.abs(y).copy()
+    s[0] = max(s[0], 1.0)
+    s[1:] = np.maximum(s[1:], 1e-8)
+    return J * s[None, :] / s[:, None]
+
+
+def test_wide_rhs_and_jacobian_match_oracle(large):
+    wl, mech, path, phi = large
+    idx = synth.sample_indices(phi.shape[0], 24, 31)
+    x = phi[idx]
+    S = chem.Solver(chem.Mechanism(path), device=0)
+    f, J = S.eval_rhs_jac(_to(x))
+    f2, _ = S.eval_rhs_jac(_to(x), jac=False)
+    torch.cuda.synchronize()
+    f, J, f2 = f.cpu().numpy(), J.cpu().numpy(), f2.cpu().numpy()
+    assert np.array_equal(f, f2)
+    M = O.Mech(path)
+    for c in range(len(idx)):
+        y = np.concatenate([[x[c, 0]], x[c, 2:]])
+        fr = M.rhs(x[c, 1], y)
+        Jr = M.jac(x[c, 1], y)
+        scale = np.abs(Jr).sum(axis=1) * np.maximum(np.abs(y), 1e-8).max() + np.abs(fr)
+        assert np.all(np.abs(f[c] - fr) <= 1e-9 * np.abs(fr) + 1e-12 * scale), c
+        A, B = _scaled(J[c], y), _scaled(Jr, y)
+        rowmax = np.abs(B).max(axis=1, keepdims=True)
+        assert np.all(np.abs(A - B) <= 1e-9 * np.abs(B) + 1e-12 * rowmax), c
+
+
+def test_wide_lu_matches_oracle_exactly(large):
+    wl, mech, path, phi = large
+    S = chem.Solver(chem.Mechanism(path), device=0)
+    n = mech.n_species + 1
+    rng = np.random.Generator(np.random.PCG64(161))
+    nb = 12
+    A = rng.normal(size=(nb, n, n)) + 2.0 * np.eye(n)[None]
+    A[1] = rng.normal(size=(n, n))                      # no diagonal help: many interchanges
+    A[2, :, 7] = np.round(A[2, :, 7])                    # ties in one column
+    b = rng.normal(size=(nb, n))
+    M = O.Mech(path)
+    for c in range(3, nb):
+        y = np.concatenate([[phi[c, 0]], phi[c, 2:]])
+        A[c] = np.eye(n) / (0.5 * 10.0 ** (-6 - c % 4)) - M.jac(phi[c, 1], y)
+    Ag, piv, info, bg = S.lu_batch(_to(A), _to(b))
+    torch.cuda.synchronize()
+    Ag, piv, info, bg = Ag.cpu().numpy(), piv.cpu().numpy(), info.cpu().numpy(), bg.cpu().numpy()
+    assert (info == 0).all()
+    for k in range(nb):
+        LU, pr, inf = O.lu(A[k])
+        assert np.array_equal(piv[k], pr), k
+        assert np.array_equal(Ag[k], LU), (k, np.max(np.abs(Ag[k] - LU)))
+        x = O.lu_solve(LU, pr, b[k])
+        assert np.max(np.abs(bg[k] - x)) <= 1e-10 * np.max(np.abs(x)), k
+
+
+def test_wide_lu_singular_info(large):
+    wl, mech, path, phi = large
+    S = chem.Solver(chem.Mechanism(path), device=0)
+    n = mech.n_species + 1
+    A = np.eye(n)[None].repeat(2, axis=0)
+    A[1, 100, :] = 0.0
+    A[1, :, 100] = 0.0
+    _, piv, info, _ = S.lu_batch(_to(A))
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0, 101]
+
+
+def _compare(phi0, gpu, ref, counts_gpu, counts_ref, frac_diff=1e-3):
+    na, nr = counts_gpu
+    ona, onr = counts_ref
+    same = (na == ona) & (nr == onr)
+    n = len(same)
+    assert (~same).sum() <= max(1, int(frac_diff * n)), "%d of %d cells took another step sequence" % ((~same).sum(), n)
+    dT = np.abs(gpu[:, 0] - ref[:, 0])
+    dY = np.abs(gpu[:, 2:] - ref[:, 2:])
+    tolY = 1e-10 + 1e-6 * np.abs(ref[:, 2:])
+    assert not (same & (dT > 1e-8 * np.abs(ref[:, 0]))).any()
+    assert not (same[:, None] & (dY > tolY)).any()
+    if (~same).any():
+        assert np.all(dT[~same] <= 10 * 1e-6 * np.abs(ref[~same, 0]))
+        assert np.all(dY[~same] <= 10 * tolY[~same])
+    assert np.array_equal(gpu[:, 1], phi0[:, 1])
+    return int(same.sum())
+
+
+def test_wide_integrate_matches_oracle(large):
+    wl, mech, path, phi = large
+    idx = synth.sample_indices(phi.shape[0], 48, 41)
+    x = np.ascontiguousarray(phi[idx])
+    S = chem.Solver(chem.Mechanism(path), chem.default_opts(schedule=chem.PERSISTENT), device=0)
+    r = S.integrate(_to(x), wl.dt)
+    torch.cuda.synchronize()
+    ref, h, na, nr, st = O.Mech(path).integrate(x, wl.dt, n_threads=NCPU)
+    assert np.array_equal(r.status.cpu().numpy(), st)
+    same = _compare(x, r.phi.cpu().numpy(), ref, (r.n_acc.cpu().numpy(), r.n_rej.cpu().numpy()), (na, nr))
+    print("large160: %d/%d cells with identical step sequence, substeps %s" % (same, len(idx), (na + nr).tolist()))
+
+
+def _run(S, x, dt, **opts):
+    S.set_opts(chem.default_opts(**opts))
+    h = torch.zeros(x.shape[0], dtype=torch.float64, device=DEV)
+    r = S.integrate(x, dt, h_io=h)
+    torch.cuda.synchronize()
+    return [r.phi.cpu().numpy(), h.cpu().numpy(), r.n_acc.cpu().numpy(), r.n_rej.cpu().numpy(),
+            r.status.cpu().numpy()]
+
+
+def _bitsame(a, b):
+    for u, v in zip(a, b):
+        assert np.array_equal(u.view(np.uint8), v.view(np.uint8))
+
+
+def test_wide_schedules_and_budget_bit_identical(large):
+    wl, mech, path, phi = large
+    x = _to(phi[:600])
+    S = chem.Solver(chem.Mechanism(path), device=0)
+    ref = _run(S, x, wl.dt, schedule=chem.PLAIN)
+    _bitsame(_run(S, x, wl.dt, schedule=chem.PERSISTENT), ref)
+    _bitsame(_run(S, x, wl.dt, schedule=chem.PERSISTENT, queue_chunk=3), ref)
+    cost = _to(np.log(np.maximum(ref[2] + ref[3], 1)).astype(np.float32))
+    S.model_set(np.zeros(4545, dtype=np.float32), None, np.linspace(0.5, 5.0, 7).astype(np.float32))
+    S.set_cost_override(cost)
+    _bitsame(_run(S, x, wl.dt, schedule=chem.PERSISTENT_BINNED), ref)
+    assert S.last_binning_used()
+    S.set_cost_override(None)
+    # HBM budget of three workspace slots: three cells in flight
+    n = mech.n_species + 1
+    slot = 2 * n * ((n + 15) // 16 * 16) * 8
+    _bitsame(_run(S, x, wl.dt, schedule=chem.PERSISTENT, hbm_budget_bytes=3 * slot + 100), ref)
+    with pytest.raises(chem.ChemError):
+        _run(S, x, wl.dt, schedule=chem.PERSISTENT, hbm_budget_bytes=slot - 1)
+
+
+def test_wide_edge_cases(large):
+    wl, mech, path, phi = large
+    S = chem.Solver(chem.Mechanism(path), chem.default_opts(schedule=chem.PERSISTENT), device=0)
+    r = S.integrate(_to(phi[:0]), wl.dt)
+    assert r.phi.shape[0] == 0
+    x = phi[:5].copy()
+    x[2, 0] = np.nan
+    r = S.integrate(_to(x), wl.dt)
+    torch.cuda.synchronize()
+    st = r.status.cpu().numpy()
+    assert st[2] == 3 and (np.delete(st, 2) == 0).all()
+    assert np.array_equal(r.phi.cpu().numpy()[2, 2:], x[2, 2:])
+    # chained steps in a graph == sequential steps
+    xs = _to(phi[:64])
+    seq = xs.clone()
+    for _ in range(2):
+        seq = S.integrate(seq, wl.dt, h_io=False).phi.clone()
+    out = torch.empty_like(xs)
+    r = S.integrate_steps(xs, wl.dt, 2, h_io=False, out=out)
+    torch.cuda.synchronize()
+    assert torch.equal(r.phi, seq)
