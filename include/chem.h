@@ -232,6 +232,14 @@ int chem_bin_order(chem_solver* s, int64_t n, const float* cost_dev, const float
 int chem_autotune(chem_solver* s, int64_t n_sample, const double* phi_sample_dev, double dt,
                   void* stream);
 
+/* Workspace of the workgroup-per-cell path (state sizes above 64): number of
+ * HBM slots (cells in flight; one per resident workgroup, at most
+ * hbm_budget_bytes in total, default half the free device memory) and bytes
+ * per slot (J and M, 2 n ld doubles with ld = n rounded up to 16). Allocates
+ * the slots if needed. Both are 0 for smaller state sizes, whose cells need
+ * no HBM workspace. */
+int chem_workspace_info(chem_solver* s, int32_t* slots, int64_t* bytes_per_slot);
+
 /* ---- kernel timing ---------------------------------------------------- */
 
 /* enable != 0: from now on record a pair of HIP events on the caller's

@@ -87,6 +87,7 @@ def lib():
             "chem_bin_edges": (i32, [_vp, i64, _vp, _vp, _vp]),
             "chem_bin_order": (i32, [_vp, i64, _vp, _vp, _vp, _vp]),
             "chem_autotune": (i32, [_vp, i64, _vp, dbl, _vp]),
+            "chem_workspace_info": (i32, [_vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
             "chem_kernel_timing": (i32, [_vp, i32]),
             "chem_kernel_times": (i32, [_vp, _vp, i32, ctypes.POINTER(i32)]),
             "chem_last_error": (ctypes.c_char_p, []),
@@ -366,6 +367,12 @@ class Solver:
                                     None if e is None else e.ctypes.data_as(_vp), _ptr(perm),
                                     _stream(self.device)))
         return perm
+
+    def workspace_info(self):
+        """(slots, bytes per slot) of the HBM workspace of large mechanisms."""
+        a, b = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().chem_workspace_info(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def kernel_timing(self, enable: bool):
         _check(lib().chem_kernel_timing(self._h, 1 if enable else 0))

@@ -846,6 +846,18 @@ int chem_autotune(chem_solver* s, int64_t n_sample, const double* phi, double dt
   return CHEM_OK;
 }
 
+int chem_workspace_info(chem_solver* s, int32_t* slots, int64_t* bytes_per_slot) {
+  if (!s || !slots || !bytes_per_slot) return fail(CHEM_EINVAL, "chem_workspace_info: bad argument");
+  *slots = 0;
+  *bytes_per_slot = 0;
+  if (!s->wide) return CHEM_OK;
+  DeviceGuard g(s->dev);
+  if (int rc = ensure_ws(s)) return rc;
+  *slots = s->wide_slots;
+  *bytes_per_slot = s->ws_stride * static_cast<int64_t>(sizeof(double));
+  return CHEM_OK;
+}
+
 // ---- kernel timing -----------------------------------------------------------
 
 int chem_kernel_timing(chem_solver* s, int32_t enable) {

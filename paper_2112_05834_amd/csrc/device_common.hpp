@@ -61,6 +61,14 @@ __device__ __forceinline__ void stage_mech(unsigned char* smem, const MechArgs& 
   __syncthreads();
 }
 
+// Order one wave's LDS accesses at a point where other lanes' writes must
+// be visible (the compiler may not move them across).
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // NASA-7 polynomials of one species at T (low range iff T < Tmid):
 // cp/R, h/(RT), g/(RT) and, with JAC, d(cp/R)/dT.
 template <bool JAC>

@@ -25,14 +25,6 @@ namespace {
 
 using namespace dev;
 
-// LDS accesses of one wave stay ordered; keep the compiler from moving them
-// across a point where other lanes' writes must be visible.
-__device__ __forceinline__ void wsync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 // LDS add whose result is not returned: nothing waits on it
 __device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);

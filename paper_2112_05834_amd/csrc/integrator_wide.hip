@@ -9,11 +9,11 @@
 // bounded by the HBM budget. Everything else of the cell (state, stage
 // vectors, concentrations, per-reaction rates) lives in LDS.
 //
-// The LU is a right-looking blocked getrf: a panel of 16 columns is factored
+// The LU is a right-looking blocked getrf: a panel of 12 columns is factored
 // in LDS with partial pivoting (first index of the largest |a|), its row
-// interchanges are applied to the other columns, the 16-row block of U is
+// interchanges are applied to the other columns, the 12-row block of U is
 // solved against the unit-lower diagonal block, and the trailing matrix
-// receives the rank-16 update in one pass through HBM. Every element sees
+// receives the rank-12 update in one pass through HBM. Every element sees
 // the same sequence of operations as in an unblocked row-swapping LU, in the
 // same order, so the factors do not depend on the blocking.
 #include <hip/hip_runtime.h>
@@ -34,14 +34,17 @@ constexpr int kT = kWideThreads;
 constexpr int kNB = kWidePanel;
 
 // Per-cell LDS area. Region A (right-hand-side buffers) and region B (LU
-// panel and U block) are never live at the same time and share storage.
+// panel and U block) are never live at the same time and share storage; so
+// do the stage input ys and the solve right-hand side v, and the stage
+// derivative fs and the trial state yn.
 struct Wide {
   double *C, *gRT, *hRT, *RB;                   // A: ns, ns, ns, 5 nr
   double *panel, *U12;                          // B: kNB ld, kNB ld
-  double *y, *f0, *fs, *ys, *yn, *v, *u[4];     // ld each
+  double *y, *f0, *fs, *ys, *yn, *v, *u[4];     // 8 distinct vectors of ld
   double* red;                                  // 16
   int* piv;                                     // ld
   int* perm;                                    // ld
+  int* sig;                                     // ld: source row of each row in one panel
   int* ired;                                    // 16
   unsigned long long* qslot;                    // 1
 };
@@ -52,10 +55,10 @@ __host__ __device__ inline int wide_region(int ns, int nr, int ld) {
   return ((a > b ? a : b) + 1) & ~1;
 }
 
-// doubles: region, 10 vectors, reduction scratch; ints: piv, perm, ired;
+// doubles: region, 8 vectors, reduction scratch; ints: piv, perm, sig, ired;
 // one 64-bit queue slot
 __host__ __device__ inline int wide_doubles(int ns, int nr, int ld) {
-  return wide_region(ns, nr, ld) + 10 * ld + 16 + (2 * ld + 16) / 2 + 2;
+  return wide_region(ns, nr, ld) + 8 * ld + 16 + (3 * ld + 16) / 2 + 2;
 }
 
 __device__ inline Wide wide_area(double* base, int ns, int nr, int ld) {
@@ -70,16 +73,17 @@ __device__ inline Wide wide_area(double* base, int ns, int nr, int ld) {
   W.y = q;
   W.f0 = q + ld;
   W.fs = q + 2 * ld;
-  W.ys = q + 3 * ld;
-  W.yn = q + 4 * ld;
-  W.v = q + 5 * ld;
-  for (int k = 0; k < 4; ++k) W.u[k] = q + (6 + k) * ld;
-  W.red = q + 10 * ld;
+  W.yn = W.fs;
+  W.v = q + 3 * ld;
+  W.ys = W.v;
+  for (int k = 0; k < 4; ++k) W.u[k] = q + (4 + k) * ld;
+  W.red = q + 8 * ld;
   int* ip = reinterpret_cast<int*>(W.red + 16);
   W.piv = ip;
   W.perm = ip + ld;
-  W.ired = ip + 2 * ld;
-  W.qslot = reinterpret_cast<unsigned long long*>(ip + 2 * ld + 16);
+  W.sig = ip + 2 * ld;
+  W.ired = ip + 3 * ld;
+  W.qslot = reinterpret_cast<unsigned long long*>(ip + 3 * ld + 16);
   return W;
 }
 
@@ -157,15 +161,17 @@ __device__ void rhs_w(const MechArgs& A, const MechLds& L, const Wide& W, double
   double dcp = 0.0;
   if (JAC) {
     dcp = bsum(Ys * dcpR * kR * rWs, W.red);
-    for (int e = t; e < n * ld; e += kT) J[e] = 0.0;
+    if (t < ld)
+      for (int c = 0; c < n; ++c) J[c * ld + t] = 0.0;
   }
   __syncthreads();
   const double lnRTp = log(kR * T / kPatm);
   for (int rx = t; rx < nr; rx += kT) reaction_rate<JAC>(L, W.C, W.gRT, W.hRT, W.RB, nr, rx, T, rT, lnT, lnRTp, Ctot);
   __syncthreads();
 
-  // species: production rates and, with JAC, the rows d(omega)/dC (thread t
-  // alone updates row t, in entry order)
+  // species: production rates and, with JAC, the rows d(omega)/dC. Thread t
+  // alone adds to row t, with atomic adds that return nothing (nothing waits
+  // on them; one thread's adds to one address apply in program order).
   double om = 0.0, wT = 0.0, td = 0.0;
   if (sp) {
     const int e0 = L.sp_off[s], e1 = L.sp_off[s + 1];
@@ -194,16 +200,16 @@ __device__ void rhs_w(const MechArgs& A, const MechLds& L, const Wide& W, double
         const double af = nu * kfT, ar = nu * krT;
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-          if (j < nre) Jr[(1 + sf[j]) * ld] += af * dPf[j];
+          if (j < nre) unsafeAtomicAdd(&Jr[(1 + sf[j]) * ld], af * dPf[j]);
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-          if (j < npr) Jr[(1 + sr[j]) * ld] += -(ar * dPr[j]);
+          if (j < npr) unsafeAtomicAdd(&Jr[(1 + sr[j]) * ld], -(ar * dPr[j]));
         const int type = (wc.x >> 28) & 3;
         if (type >= 1) {
           const double ab = nu * q0b;
           td = td + ab;
           const int eoff = wc.w & 0xffff, neff = (wc.w >> 16) & 0xff;
-          for (int q = 0; q < neff; ++q) Jr[(1 + L.eff_sp[eoff + q]) * ld] += ab * L.eff_am1[eoff + q];
+          for (int q = 0; q < neff; ++q) unsafeAtomicAdd(&Jr[(1 + L.eff_sp[eoff + q]) * ld], ab * L.eff_am1[eoff + q]);
         }
       }
     }
@@ -218,22 +224,24 @@ __device__ void rhs_w(const MechArgs& A, const MechLds& L, const Wide& W, double
     return;
   }
 
-  // chain rule from d(omega)/dC and d(omega)/dT to y = (T, Y)
+  // chain rule from d(omega)/dC and d(omega)/dT to y = (T, Y): the adds
+  // complete (release), then every thread sees them past its L1 (acquire)
+  __threadfence();
   __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   double sv = 0.0;
   if (sp) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int k = 0;
-    for (; k + 3 < ns; k += 4) {
-      a0 = fma(J[(1 + k) * ld + t], W.C[k], a0);
-      a1 = fma(J[(2 + k) * ld + t], W.C[k + 1], a1);
-      a2 = fma(J[(3 + k) * ld + t], W.C[k + 2], a2);
-      a3 = fma(J[(4 + k) * ld + t], W.C[k + 3], a3);
+    // four accumulators (k mod 4), eight loads in flight
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < ns; k0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = k0 + q < ns ? J[(1 + k0 + q) * ld + t] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (k0 + q < ns) a[q & 3] = fma(v[q], W.C[k0 + q], a[q & 3]);
     }
-    if (k < ns) a0 = fma(J[(1 + k) * ld + t], W.C[k], a0);
-    if (k + 1 < ns) a1 = fma(J[(2 + k) * ld + t], W.C[k + 1], a1);
-    if (k + 2 < ns) a2 = fma(J[(3 + k) * ld + t], W.C[k + 2], a2);
-    sv = ((a0 + a1) + (a2 + a3)) + td * Ctot;
+    sv = ((a[0] + a[1]) + (a[2] + a[3])) + td * Ctot;
   }
   const double HS = bsum(hRT * sv, W.red);
   const double HT = bsum(hRT * td, W.red);
@@ -241,18 +249,16 @@ __device__ void rhs_w(const MechArgs& A, const MechLds& L, const Wide& W, double
   double JT = 0.0;
   if (sp) {
     const double* col = J + t * ld + 1;    // column t, rows 1..ns
-    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
-    int q = 0;
-    for (; q + 3 < ns; q += 4) {
-      c0 = fma(W.hRT[q], col[q], c0);
-      c1 = fma(W.hRT[q + 1], col[q + 1], c1);
-      c2 = fma(W.hRT[q + 2], col[q + 2], c2);
-      c3 = fma(W.hRT[q + 3], col[q + 3], c3);
+    double c[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q0 = 0; q0 < ns; q0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = q0 + q < ns ? col[q0 + q] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q0 + q < ns) c[q & 3] = fma(W.hRT[q0 + q], v[q], c[q & 3]);
     }
-    if (q < ns) c0 = fma(W.hRT[q], col[q], c0);
-    if (q + 1 < ns) c1 = fma(W.hRT[q + 1], col[q + 1], c1);
-    if (q + 2 < ns) c2 = fma(W.hRT[q + 2], col[q + 2], c2);
-    const double cs = (c0 + c1) + (c2 + c3);
+    const double cs = (c[0] + c[1]) + (c[2] + c[3]);
     const double dQdY = kR * T * ((rho * rWs) * (cs + HT) - (Wbar * rWs) * HS);
     const double drcp = rho * cpR * kR * rWs - rcp * Wbar * rWs;
     JT = -(dQdY + fT * drcp) / rcp;
@@ -260,11 +266,20 @@ __device__ void rhs_w(const MechArgs& A, const MechLds& L, const Wide& W, double
   __syncthreads();
   if (sp) {
     const double Wi_rho = A.W[s] / rho;
-    for (int k = 0; k < ns; ++k) {
-      const double rWk = L.rW[k];
-      const double D = J[(1 + k) * ld + t] + td;
-      const double dw = (rho * rWk) * D - (Wbar * rWk) * sv;
-      J[(1 + k) * ld + t] = Wi_rho * dw + fY * Wbar * rWk;
+    for (int k0 = 0; k0 < ns; k0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = k0 + q < ns ? J[(1 + k0 + q) * ld + t] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = k0 + q;
+        if (k < ns) {
+          const double rWk = L.rW[k];
+          const double D = v[q] + td;
+          const double dw = (rho * rWk) * D - (Wbar * rWk) * sv;
+          J[(1 + k) * ld + t] = Wi_rho * dw + fY * Wbar * rWk;
+        }
+      }
     }
     J[t] = Wi_rho * (wT - sv / T) + fY / T;   // (t, 0)
     J[t * ld] = JT;                           // (0, t)
@@ -280,72 +295,103 @@ __device__ void rhs_w(const MechArgs& A, const MechLds& L, const Wide& W, double
 // lower, below the diagonal) and U. W.piv[k] = row interchanged with row k
 // at step k, W.perm = the resulting row order. Returns the first zero pivot
 // column + 1 (0 if none); such a column is left unreduced, as getrf does.
+// The panel is factored by wave 0 alone (no workgroup barrier per column);
+// the whole workgroup applies its interchanges, solves the U block and
+// updates the trailing matrix.
 __device__ int lu_w(double* M, int n, int ld, const Wide& W) {
   const int t = threadIdx.x;
-  for (int i = t; i < ld; i += kT) W.perm[i] = i;
+  if (t < ld) W.perm[t] = t;
   int info = 0;
   for (int k0 = 0; k0 < n; k0 += kNB) {
     const int nb = min(kNB, n - k0);
-    for (int e = t; e < nb * ld; e += kT) {
-      const int c = e / ld, r = e - c * ld;
-      W.panel[e] = (r >= k0 && r < n) ? M[(k0 + c) * ld + r] : 0.0;
+    if (t < ld) {
+      const bool in = t >= k0 && t < n;
+      for (int c = 0; c < nb; ++c) W.panel[c * ld + t] = in ? M[(k0 + c) * ld + t] : 0.0;
+      W.sig[t] = t;
     }
     __syncthreads();
-    for (int c = 0; c < nb; ++c) {
-      const int k = k0 + c;
-      double* pc = W.panel + c * ld;
-      double key = -1.0;
-      int idx = 1 << 30;
-      if (t >= k && t < n) {
-        const double av = fabs(pc[t]);
-        // a NaN on the diagonal stays the pivot; elsewhere it never wins
-        key = (av != av) ? (t == k ? INFINITY : -1.0) : av;
-        idx = t;
-      }
-      const int pv = bargmax(key, idx, W.red, W.ired);
-      if (t == 0) {
-        W.piv[k] = pv;
-        const int tmp = W.perm[k];
-        W.perm[k] = W.perm[pv];
-        W.perm[pv] = tmp;
-      }
-      if (pv != k && t < nb) {
-        double* q = W.panel + t * ld;
-        const double tmp = q[k];
-        q[k] = q[pv];
-        q[pv] = tmp;
-      }
-      __syncthreads();
-      const double akk = pc[k];
-      if (akk == 0.0) {
-        if (!info) info = k + 1;
-        continue;
-      }
-      if (t > k && t < n) {
-        const double l = pc[t] / akk;
-        pc[t] = l;
-        for (int c2 = c + 1; c2 < nb; ++c2) {
-          double* q = W.panel + c2 * ld;
-          q[t] = q[t] - l * q[k];
+    if (t < 64) {
+      for (int c = 0; c < nb; ++c) {
+        const int k = k0 + c;
+        double* pc = W.panel + c * ld;
+        // first index of the largest |a| among rows k..n-1 (a NaN on the
+        // diagonal stays the pivot; elsewhere it never wins)
+        double key = -1.0;
+        int idx = 1 << 30;
+        for (int r = k + t; r < n; r += 64) {
+          const double av = fabs(pc[r]);
+          const double kv = (av != av) ? (r == k ? INFINITY : -1.0) : av;
+          if (kv > key) {
+            key = kv;
+            idx = r;
+          }
         }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          const double ok = __shfl_xor(key, off);
+          const int oi = __shfl_xor(idx, off);
+          if (ok > key || (ok == key && oi < idx)) {
+            key = ok;
+            idx = oi;
+          }
+        }
+        const int pv = idx;
+        if (t == 0) {
+          W.piv[k] = pv;
+          const int tmp = W.perm[k];
+          W.perm[k] = W.perm[pv];
+          W.perm[pv] = tmp;
+          const int tms = W.sig[k];
+          W.sig[k] = W.sig[pv];
+          W.sig[pv] = tms;
+        }
+        if (pv != k && t < nb) {
+          double* q = W.panel + t * ld;
+          const double tmp = q[k];
+          q[k] = q[pv];
+          q[pv] = tmp;
+        }
+        wsync();
+        const double akk = pc[k];
+        if (akk == 0.0) {
+          if (!info) info = k + 1;
+          continue;
+        }
+        for (int r = k + 1 + t; r < n; r += 64) {
+          const double l = pc[r] / akk;
+          pc[r] = l;
+          for (int c2 = c + 1; c2 < nb; ++c2) {
+            double* q = W.panel + c2 * ld;
+            q[r] = q[r] - l * q[k];
+          }
+        }
+        wsync();
       }
-      __syncthreads();
+      if (t == 0) W.ired[15] = info;
     }
+    __syncthreads();
+    info = W.ired[15];
     // panel back to HBM, and its interchanges on the other columns
-    for (int e = t; e < nb * ld; e += kT) {
-      const int c = e / ld, r = e - c * ld;
-      if (r >= k0 && r < n) M[(k0 + c) * ld + r] = W.panel[e];
-    }
+    if (t < ld && t >= k0 && t < n)
+      for (int c = 0; c < nb; ++c) M[(k0 + c) * ld + t] = W.panel[c * ld + t];
+    // The panel's interchanges compose to row i <- row sig[i]; only rows
+    // k0..k0+nb-1 and their pivot rows can move. All sources are read before
+    // any destination is written.
     for (int j = t; j < n; j += kT) {
       if (j >= k0 && j < k0 + nb) continue;
       double* col = M + j * ld;
-      for (int c = 0; c < nb; ++c) {
-        const int k = k0 + c, pv = W.piv[k];
-        if (pv != k) {
-          const double tmp = col[k];
-          col[k] = col[pv];
-          col[pv] = tmp;
-        }
+      double va[kNB], vb[kNB];
+#pragma unroll
+      for (int c = 0; c < kNB; ++c) {
+        const int ia = k0 + c, ib = c < nb ? W.piv[k0 + c] : ia;
+        va[c] = (c < nb && W.sig[ia] != ia) ? col[W.sig[ia]] : 0.0;
+        vb[c] = (c < nb && W.sig[ib] != ib) ? col[W.sig[ib]] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < kNB; ++c) {
+        const int ia = k0 + c, ib = c < nb ? W.piv[k0 + c] : ia;
+        if (c < nb && W.sig[ia] != ia) col[ia] = va[c];
+        if (c < nb && W.sig[ib] != ib) col[ib] = vb[c];
       }
     }
     __syncthreads();
@@ -372,16 +418,34 @@ __device__ int lu_w(double* M, int n, int ld, const Wide& W) {
         }
       }
       __syncthreads();
-      // trailing update A22 -= L21 U12, rows fastest (coalesced)
-      const long long mm = static_cast<long long>(m) * m;
-      for (long long e = t; e < mm; e += kT) {
-        const int jj = static_cast<int>(e / m);
-        const int r = j0 + static_cast<int>(e - static_cast<long long>(jj) * m);
-        const int j = j0 + jj;
-        double av = M[j * ld + r];
-        const double* u = W.U12 + jj * kNB;
-        for (int q = 0; q < nb; ++q) av = av - W.panel[q * ld + r] * u[q];
-        M[j * ld + r] = av;
+      // trailing update A22 -= L21 U12: threads 0..127 and 128..255 take
+      // alternate columns; consecutive threads take consecutive rows
+      const int half = t >> 7, rl = t & 127;
+      for (int rb = rl; rb < m; rb += 128) {
+        const int r = j0 + rb;
+        double lr[kNB];
+#pragma unroll
+        for (int q = 0; q < kNB; ++q) lr[q] = q < nb ? W.panel[q * ld + r] : 0.0;
+        // eight columns per round: loads first, then the updates, then stores
+        for (int jb = half; jb < m; jb += 16) {
+          double av[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int jj = jb + 2 * i;
+            av[i] = jj < m ? M[(j0 + jj) * ld + r] : 0.0;
+          }
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int jj = jb + 2 * i;
+            if (jj < m) {
+              const double* u = W.U12 + jj * kNB;
+#pragma unroll
+              for (int q = 0; q < kNB; ++q)
+                if (q < nb) av[i] = av[i] - lr[q] * u[q];
+              M[(j0 + jj) * ld + r] = av[i];
+            }
+          }
+        }
       }
       __syncthreads();
     }
@@ -390,49 +454,77 @@ __device__ int lu_w(double* M, int n, int ld, const Wide& W) {
 }
 
 // x = M^-1 b with the factors of lu_w (b, x: LDS vectors, distinct).
-// Forward substitution in column blocks (each element receives its terms in
-// ascending column order), then backward in column blocks from the bottom.
+// Forward substitution in blocks of kSB columns (each element receives its
+// terms in ascending column order), then backward in blocks from the
+// bottom. Wave 0 solves the diagonal triangle with the block's factors
+// loaded up front; every thread then updates its row with kSB independent
+// loads in flight.
+constexpr int kSB = 32;
+
 __device__ void solve_w(const double* M, int n, int ld, const Wide& W, const double* b, double* x) {
   const int t = threadIdx.x;
   if (t < n) x[t] = b[W.perm[t]];
   __syncthreads();
-  for (int k0 = 0; k0 < n; k0 += kNB) {
-    const int nb = min(kNB, n - k0);
+  for (int k0 = 0; k0 < n; k0 += kSB) {
+    const int nb = min(kSB, n - k0);
     if (t < 64) {
+      double lc[kSB];
+#pragma unroll
+      for (int q = 0; q < kSB; ++q) lc[q] = (q + 1 < nb && t > q && t < nb) ? M[(k0 + q) * ld + k0 + t] : 0.0;
       double xv = t < nb ? x[k0 + t] : 0.0;
-      for (int q = 0; q + 1 < nb; ++q) {
-        const double z = __shfl(xv, q);
-        if (t > q && t < nb) xv = xv - M[(k0 + q) * ld + k0 + t] * z;
+#pragma unroll
+      for (int q = 0; q + 1 < kSB; ++q) {
+        if (q + 1 < nb) {
+          const double z = __shfl(xv, q);
+          if (t > q && t < nb) xv = xv - lc[q] * z;
+        }
       }
       if (t < nb) x[k0 + t] = xv;
     }
     __syncthreads();
     for (int r = k0 + nb + t; r < n; r += kT) {
+      double lv[kSB];
+#pragma unroll
+      for (int q = 0; q < kSB; ++q) lv[q] = q < nb ? M[(k0 + q) * ld + r] : 0.0;
       double a = x[r];
-      for (int q = 0; q < nb; ++q) a = a - M[(k0 + q) * ld + r] * x[k0 + q];
+#pragma unroll
+      for (int q = 0; q < kSB; ++q)
+        if (q < nb) a = a - lv[q] * x[k0 + q];
       x[r] = a;
     }
     __syncthreads();
   }
-  for (int k0 = ((n - 1) / kNB) * kNB; k0 >= 0; k0 -= kNB) {
-    const int nb = min(kNB, n - k0);
+  for (int k0 = ((n - 1) / kSB) * kSB; k0 >= 0; k0 -= kSB) {
+    const int nb = min(kSB, n - k0);
     if (t < 64) {
+      double uc[kSB];
+#pragma unroll
+      for (int q = 0; q < kSB; ++q) uc[q] = (q < nb && t < q) ? M[(k0 + q) * ld + k0 + t] : 0.0;
+      const double dg = t < nb ? M[(k0 + t) * ld + k0 + t] : 1.0;
       double xv = t < nb ? x[k0 + t] : 0.0;
-      for (int q = nb - 1; q >= 0; --q) {
-        const double d = (t == q) ? xv / M[(k0 + q) * ld + k0 + q] : 0.0;
-        const double z = __shfl(d, q);
-        if (t == q) {
-          xv = z;
-        } else if (t < q) {
-          xv = xv - M[(k0 + q) * ld + k0 + t] * z;
+#pragma unroll
+      for (int q = kSB - 1; q >= 0; --q) {
+        if (q < nb) {
+          const double d = (t == q) ? xv / dg : 0.0;
+          const double z = __shfl(d, q);
+          if (t == q) {
+            xv = z;
+          } else if (t < q) {
+            xv = xv - uc[q] * z;
+          }
         }
       }
       if (t < nb) x[k0 + t] = xv;
     }
     __syncthreads();
     for (int r = t; r < k0; r += kT) {
+      double uv[kSB];
+#pragma unroll
+      for (int q = 0; q < kSB; ++q) uv[q] = q < nb ? M[(k0 + q) * ld + r] : 0.0;
       double a = x[r];
-      for (int q = 0; q < nb; ++q) a = a - M[(k0 + q) * ld + r] * x[k0 + q];
+#pragma unroll
+      for (int q = 0; q < kSB; ++q)
+        if (q < nb) a = a - uv[q] * x[k0 + q];
       x[r] = a;
     }
     __syncthreads();
@@ -473,9 +565,16 @@ __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, 
       break;
     }
     const double g = 1.0 / (kGamma * hc);
-    for (int e = t; e < n * ld; e += kT) {
-      const int c = e / ld, r = e - c * ld;
-      M[e] = (r == c ? g : 0.0) - J[e];
+    if (t < ld) {
+      // eight independent loads in flight per thread
+      for (int c0 = 0; c0 < n; c0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = c0 + q < n ? J[(c0 + q) * ld + t] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (c0 + q < n) M[(c0 + q) * ld + t] = (t == c0 + q ? g : 0.0) - v[q];
+      }
     }
     __syncthreads();
     const int info = lu_w(M, n, ld, W);
@@ -611,7 +710,7 @@ __device__ void run_cell_w(const IntegrateArgs& a, const MechLds& L, const Wide&
 // Each workgroup owns workspace slot blockIdx.x. Plain: cells blockIdx.x,
 // blockIdx.x + gridDim.x, ... (static); persistent: chunks from the queue.
 template <bool PERSIST>
-__global__ void __launch_bounds__(256) k_integrate_wide(IntegrateArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_integrate_wide(IntegrateArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   stage_mech(smem, a.m);
   const MechLds L = mech_views(smem, a.m);

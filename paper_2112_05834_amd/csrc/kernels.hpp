@@ -91,7 +91,7 @@ struct Variant {
 };
 constexpr int kWideNN = 256;          // largest n of the workgroup kernel
 constexpr int kWideThreads = 256;     // threads per cell
-constexpr int kWidePanel = 16;        // LU panel width
+constexpr int kWidePanel = 12;        // LU panel width
 inline int wide_ld(int n) { return (n + 15) & ~15; }
 // LDS bytes of the workgroup kernel's per-cell area (after the mechanism prefix)
 int wide_cell_bytes(int ns, int nr, int ld);
