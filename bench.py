@@ -151,6 +151,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedules", default="plain,persistent,binned,truebins")
+    ap.add_argument("--autotune", type=int, default=0, metavar="CELLS",
+                    help="pick launch shape and queue chunk by timing a seeded sample of this many cells first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -195,6 +197,19 @@ def main():
             (training["samples"], training["log_s"], training["train_s"], training["mse_ln_substeps"],
              training["target_var"]))
 
+    tuned = None
+    if args.autotune > 0:
+        idx = synth.sample_indices(n_cells, args.autotune, 11)
+        sample = torch.from_numpy(np.ascontiguousarray(phi[idx])).to("cuda:0")
+        tuned = {}
+        for sched in ("persistent",):
+            S.set_opts(chem.default_opts(schedule=chem.PERSISTENT))
+            S.autotune(sample, wl.dt)
+            o = S.opts
+            tuned = {"waves_per_block": o.waves_per_block, "queue_chunk": o.queue_chunk,
+                     "cells_per_wave": o.cells_per_wave, "sample_cells": len(idx)}
+        log("autotuned on %d cells: %s" % (len(idx), tuned))
+
     codes = {"plain": chem.PLAIN, "persistent": chem.PERSISTENT, "binned": chem.PERSISTENT_BINNED,
              "truebins": chem.PERSISTENT_BINNED}
     results = {}
@@ -207,8 +222,12 @@ def main():
             true_cost = torch.from_numpy(np.log(np.maximum(ref["na"] + ref["nr"], 1)).astype(np.float32)).to(
                 "cuda:0")
             S.set_cost_override(true_cost)
+        extra = {}
+        if tuned and sched != "plain":
+            extra = {"waves_per_block": tuned["waves_per_block"], "queue_chunk": tuned["queue_chunk"],
+                     "cells_per_wave": tuned["cells_per_wave"]}
         r, wall, ms, kms = time_schedule(S, chem, torch, x, wl.dt, args.steps, args.warmup, args.chain,
-                                         schedule=codes[sched])
+                                         schedule=codes[sched], **extra)
         used = S.last_binning_used() if codes[sched] == chem.PERSISTENT_BINNED else None
         if sched == "truebins":
             S.set_cost_override(None)
@@ -270,6 +289,8 @@ def main():
         line["speedup_vs_plain"] = R["cells_per_s"] / results["plain"]["cells_per_s"]
     if training is not None:
         line["training"] = training
+    if tuned is not None:
+        line["autotuned"] = tuned
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(path, phi, wl.dt, args.cpu_seconds, 7)
     print(json.dumps(line), flush=True)
