@@ -47,6 +47,17 @@ def flops_per_launch(work, n, n_acc, n_rej):
     return starts * f_start + att * f_att
 
 
+def bytes_per_launch_wide(n, n_acc, n_rej, cells):
+    """Algorithmic HBM bytes of one launch of the workgroup-per-cell kernel
+    (J and M of each cell live in HBM): per attempted step, forming M (read
+    J, write M), one read and one write of M by the LU and four solves each
+    reading the factors, 64 n^2 bytes; per step start, writing J and the
+    chain rule's read and write, 24 n^2 bytes; per cell, phi in and out."""
+    att = float((n_acc + n_rej).sum())
+    starts = float(n_acc.sum())
+    return 64.0 * n * n * att + 24.0 * n * n * starts + 2.0 * 8 * (n + 1) * cells
+
+
 def measured_traffic(kernel_src):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel source (else None)."""
@@ -92,15 +103,15 @@ def time_schedule(S, chem, torch, x, dt, steps, warmup, chain, **opts):
     return r, wall, ms, kms
 
 
-def train_model(S, chem, torch, synth, wl, mech, seeds, log):
+def train_model(S, chem, torch, synth, wl, mech, seeds, log, n_cells):
     """Log (features, ln substeps) of every cell of other seeds' states in
     one persistent step each, then train the predictor on all of them."""
     t0 = time.perf_counter()
     feats, targ = [], []
     S.set_opts(chem.default_opts(schedule=chem.PERSISTENT))
     for sd in seeds:
-        phi = synth.generate_states(mech, wl.n_cells, wl.pressure, wl.recipe, sd)
-        x = torch.from_numpy(phi).to("cuda:0")
+        phi = synth.generate_states(mech, wl.n_cells, wl.pressure, wl.recipe, sd)[:n_cells]
+        x = torch.from_numpy(phi.copy()).to("cuda:0")
         S.log_enable(x.shape[0])
         S.integrate(x, wl.dt, h_io=False)
         f, t = S.log_fetch(x.shape[0])
@@ -148,6 +159,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="spray54_262144")
     ap.add_argument("--chain", type=int, default=1, help="chemistry steps per graph launch (chained in a HIP graph)")
+    ap.add_argument("--cells", type=int, default=0,
+                    help="use only the first CELLS cells of the workload (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedules", default="plain,persistent,binned,truebins")
@@ -171,7 +184,7 @@ def main():
         print("bench: " + msg, file=sys.stderr, flush=True)
 
     d = tempfile.mkdtemp(prefix="chem_bench_")
-    wl, mech, path, phi = synth.workload_inputs(args.workload, d)
+    wl, mech, path, phi = synth.workload_inputs(args.workload, d, args.cells if args.cells > 0 else None)
     M = chem.Mechanism(path)
     S = chem.Solver(M, chem.default_opts(), device=0)
     x = torch.from_numpy(phi).to("cuda:0")
@@ -192,7 +205,8 @@ def main():
 
     training = None
     if "binned" in scheds or "truebins" in scheds:
-        training = train_model(S, chem, torch, synth, wl, mech, TRAIN_SEEDS.get(args.workload, [1040, 1041]), log)
+        training = train_model(S, chem, torch, synth, wl, mech, TRAIN_SEEDS.get(args.workload, [1040, 1041]), log,
+                               n_cells)
         log("model trained on %d samples: log %.1f s, train %.1f s, mse %.3f (target variance %.3f)" %
             (training["samples"], training["log_s"], training["train_s"], training["mse_ln_substeps"],
              training["target_var"]))
@@ -245,13 +259,14 @@ def main():
     R = results[head]
     ref = results.get("plain", R)
     flops = flops_per_launch(work, n, R["na"], R["nr"])
+    wide = n > 64
     if args.chain > 1:
         kern_s = achieved = None
     else:
         kern_s = float(np.mean(R["kms"])) / 1e3 if len(R["kms"]) else float(np.mean(R["ms"])) / 1e3
         achieved = flops / kern_s
     traffic = measured_traffic(os.path.join(ROOT, "paper_2112_05834_amd", "csrc", "integrator.hip"))
-    if args.workload != "spray54_262144" or args.chain > 1:
+    if args.workload != "spray54_262144" or args.chain > 1 or args.cells > 0:
         traffic = None
     steps_total = args.steps * args.chain
     line = {
@@ -285,6 +300,17 @@ def main():
                      "p99": float(np.percentile(ref["na"] + ref["nr"], 99)),
                      "max": int((ref["na"] + ref["nr"]).max())},
     }
+    if wide:
+        # J and M live in HBM: the bandwidth roof applies, FP64 is secondary
+        hb = bytes_per_launch_wide(n, R["na"], R["nr"], n_cells)
+        fp64 = line["roofline"]
+        line["roofline"] = {"bound": "hbm", "achieved": None if kern_s is None else hb / kern_s / 1e9,
+                            "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                            "frac": None if kern_s is None else hb / kern_s / HBM_PEAK, "traffic": None,
+                            "kernel": "k_integrate_wide (%s schedule)" % head, "bytes_per_launch": hb,
+                            "kernel_ms": fp64["kernel_ms"],
+                            "fp64": {"achieved": fp64["achieved"], "peak": fp64["peak"], "unit": "TFLOP/s",
+                                     "frac": fp64["frac"], "flops_per_launch": flops}}
     if "plain" in results and head != "plain":
         line["speedup_vs_plain"] = R["cells_per_s"] / results["plain"]["cells_per_s"]
     if training is not None:
