@@ -167,6 +167,64 @@ __device__ __forceinline__ CellArea cell_area(double* base, int nr, int ns) {
   return c;
 }
 
+// Reaction-major Jacobian assembly (state sizes above 32, one cell per
+// wave): the lane of reaction rx forms its concentration partials once,
+// dq/dC_j = kf theta dPf_j for reactants and -kr theta dPr_j for products,
+// and adds nu_i dq/dC_j to J(1+i, 1+j) for every species i and j of the
+// reaction (nu_i = -order on the reactant side, +order on the product side),
+// plus nu_i (alpha_k - 1) q0 dtheta/d[M] for the listed third-body
+// efficiencies. LDS adds that return nothing; the lane-to-reaction mapping
+// is fixed, so the order of the adds into each element is fixed.
+template <int NN>
+__device__ __forceinline__ void jac_scatter(const MechLds& L, const double* C, const double* RB, int nr, int rx,
+                                            double* J) {
+  const uint4 w = L.rint[rx];
+  const int nre = (w.x >> 24) & 0xf, npr = (w.y >> 24) & 0xf;
+  double Pf, Pr, dPf[3], dPr[3];
+  int sf[3], sr[3];
+  mass_action(C, w.x, w.z, nre, Pf, dPf, sf);
+  mass_action(C, w.y, w.z >> 12, npr, Pr, dPr, sr);
+  const double kfT = RB[nr + rx], krT = RB[2 * nr + rx];
+  double dq[6];
+  int col[6];
+  bool cv[6];
+  double nu[6];
+  int row[6];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    dq[j] = kfT * dPf[j];
+    dq[3 + j] = -(krT * dPr[j]);
+    col[j] = sf[j];
+    col[3 + j] = sr[j];
+    cv[j] = j < nre;
+    cv[3 + j] = j < npr;
+    nu[j] = -static_cast<double>((w.z >> (4 * j)) & 0xf);
+    nu[3 + j] = static_cast<double>((w.z >> (12 + 4 * j)) & 0xf);
+    row[j] = sf[j];
+    row[3 + j] = sr[j];
+  }
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    if (!cv[a]) continue;
+    double* Jr = J + (1 + row[a]) * NN + 1;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+      if (cv[b]) lds_add(&Jr[col[b]], nu[a] * dq[b]);
+  }
+  const int type = (w.x >> 28) & 3;
+  if (type >= 1) {
+    const double q0b = RB[3 * nr + rx];
+    const int eoff = w.w & 0xffff, neff = (w.w >> 16) & 0xff;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      if (!cv[a]) continue;
+      double* Jr = J + (1 + row[a]) * NN + 1;
+      const double ab = nu[a] * q0b;
+      for (int q = 0; q < neff; ++q) lds_add(&Jr[L.eff_sp[eoff + q]], ab * L.eff_am1[eoff + q]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // one cell
 // ---------------------------------------------------------------------------
@@ -174,6 +232,11 @@ template <int NN, int G>
 struct Cell {
   static_assert(G >= NN, "one state component per lane");
   using Gp = Grp<G>;
+  // Reaction-major Jacobian assembly for state sizes above 32 (only 64-lane
+  // groups exist there); smaller sizes, which also run several cells per
+  // wave, keep the species-major assembly, whose order of additions does
+  // not depend on the group width.
+  static constexpr bool kScatter = NN > 32;
 
   // f = dy/dt at y (this lane's component); with JAC also the analytical
   // Jacobian df/dy, written row-major into ca.J (complete on return).
@@ -221,6 +284,7 @@ struct Cell {
       const int rx = r0 + i;
       if (rx >= nr) break;
       reaction_rate<JAC>(L, ca.C, ca.gRT, ca.hRT, ca.RB, nr, rx, T, rT, lnT, lnRTp, Ctot);
+      if constexpr (JAC && kScatter) jac_scatter<NN>(L, ca.C, ca.RB, nr, rx, ca.J);
     }
     wsync();
 
@@ -239,6 +303,18 @@ struct Cell {
           const unsigned ent = L.sp_ent[e];
           const double nu = static_cast<double>(static_cast<int>(ent >> 12) - 8);
           om = om + nu * ca.RB[ent & 0xfff];
+        }
+      } else if (kScatter) {
+        // the Jacobian rows were assembled reaction by reaction; q0 dtheta/d[M]
+        // is zero for elementary reactions
+#pragma unroll 4
+        for (int e = e0; e < e1; ++e) {
+          const unsigned ent = L.sp_ent[e];
+          const int rx = ent & 0xfff;
+          const double nu = static_cast<double>(static_cast<int>(ent >> 12) - 8);
+          om = om + nu * ca.RB[rx];
+          wT = wT + nu * ca.RB[4 * nr + rx];
+          td = td + nu * ca.RB[3 * nr + rx];
         }
       } else {
         unsigned ent = e0 < e1 ? L.sp_ent[e0] : 0u;
