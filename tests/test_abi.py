@@ -56,3 +56,36 @@ def test_default_opts():
     from paper_2112_05834_amd import chem
     o = chem.default_opts()
     assert (o.rtol, o.atol, o.max_steps, o.schedule) == (1e-6, 1e-10, 100000, 0)
+
+
+def test_null_and_bad_arguments_are_errors_not_crashes():
+    from paper_2112_05834_amd import chem
+    L = chem.lib()
+    h = ctypes.c_void_p()
+    assert L.chem_mech_load(None, ctypes.byref(h)) == -1
+    assert L.chem_solver_create(None, None, 0, ctypes.byref(h)) == -1
+    assert L.chem_integrate(None, 1, 1e-6, None, None, None, None, None, None, None) == -1
+    assert L.chem_model_train(None, 1, None, None, None, None) == -1
+    assert L.chem_bin_order(None, 1, None, None, None, None) == -1
+    n = ctypes.c_int32()
+    assert L.chem_kernel_times(None, None, 0, ctypes.byref(n)) == -1
+    assert L.chem_last_error()          # a message is set
+    L.chem_mech_free(None)               # NULL-safe
+    L.chem_solver_free(None)
+
+
+def test_too_many_species_is_a_mechanism_error(tmp_path):
+    """Species beyond what the kernels address (255) are rejected at load,
+    with a message, not later on the device."""
+    from paper_2112_05834_amd import chem
+    poly = "2.5 0 0 0 0 100 4"
+    lines = ["chemmech 1", "elements 1", "E0 0.001", "species 300"]
+    for k in range(300):
+        lines += ["S%d 0.001 200 1000 6000 1" % k, poly, poly]
+    lines += ["reactions 0", "end"]
+    p = tmp_path / "big.mech"
+    p.write_text("\n".join(lines) + "\n")
+    with pytest.raises(chem.ChemError) as e:
+        chem.Mechanism(str(p))
+    assert e.value.code == -2
+    assert "species" in str(e.value)
