@@ -8,8 +8,8 @@
 * Binned integration: phi, h, counters and status bit-identical to the
   unbinned schedules, with a trained model, with true-cost bins and on the
   non-finite-prediction fallback.
-* Gain: on cells whose cost rises with their index, longest-first bins beat
-  the queue in index order.
+
+The timing test of what the bins gain is collected last, in its own file.
 """
 import numpy as np
 import pytest
@@ -241,38 +241,3 @@ def test_binning_without_model_uses_queue_order(spray):
     a = _run(S, x, wl.dt, schedule=chem.PERSISTENT_BINNED)
     assert not S.last_binning_used()
     _bitsame(a, _run(S, x, wl.dt, schedule=chem.PLAIN))
-
-
-def _time(S, x, dt, reps=3, **opts):
-    S.set_opts(chem.default_opts(**opts))
-    out = torch.empty_like(x)
-    S.integrate(x, dt, h_io=False, out=out)
-    torch.cuda.synchronize()
-    best = 1e30
-    for _ in range(reps):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        S.integrate(x, dt, h_io=False, out=out)
-        b.record()
-        torch.cuda.synchronize()
-        best = min(best, a.elapsed_time(b))
-    return best
-
-
-def test_binning_gain_on_cost_sorted_cells(trained, spray):
-    """Cells ordered by ascending true cost: the index-order queue starts the
-    longest cells last; longest-first bins (predicted or true) finish sooner."""
-    wl = spray[0]
-    S, x, ref = trained
-    order = np.argsort(ref[2] + ref[3], kind="stable")
-    xs = x[_to(order.astype(np.int64))].contiguous()
-    t_plain_q = _time(S, xs, wl.dt, schedule=chem.PERSISTENT)
-    t_binned = _time(S, xs, wl.dt, schedule=chem.PERSISTENT_BINNED)
-    assert S.last_binning_used()
-    cost = _to(np.log(np.maximum((ref[2] + ref[3])[order], 1)).astype(np.float32))
-    S.set_cost_override(cost)
-    t_true = _time(S, xs, wl.dt, schedule=chem.PERSISTENT_BINNED)
-    S.set_cost_override(None)
-    print("queue order %.2f ms, predicted bins %.2f ms, true-cost bins %.2f ms" % (t_plain_q, t_binned, t_true))
-    assert t_binned < t_plain_q
-    assert t_true < t_plain_q

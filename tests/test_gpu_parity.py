@@ -152,6 +152,44 @@ def test_integrate_spray_full_size_sampled(spray):
     assert np.abs(out[:, 2:].sum(axis=1) - 1.0).max() < 1e-12
 
 
+@pytest.fixture(scope="module")
+def heavy(tmp_path_factory):
+    d = str(tmp_path_factory.mktemp("heavy"))
+    return synth.workload_inputs("spray54_heavytail_1048576", d)
+
+
+def test_heavytail_chained_full_size_sampled(heavy):
+    """1 048 576 heavy-tailed cells, ten chained steps captured in one HIP
+    graph on the persistent queue with 4 waves per block and chunk 1: 40
+    random cells and the 8 costliest against the oracle stepping ten times
+    with the step size carried over. A cell's counters are summed over the
+    ten steps, so up to 5% of the sample may differ in them."""
+    wl, mech, path, phi = heavy
+    S = chem.Solver(chem.Mechanism(path), chem.default_opts(schedule=chem.PERSISTENT, waves_per_block=4,
+                                                           queue_chunk=1), device=0)
+    x = _to(phi)
+    h = torch.zeros(phi.shape[0], dtype=torch.float64, device=DEV)
+    r = S.integrate_steps(x, wl.dt, wl.n_steps, h_io=h, out=torch.empty_like(x))
+    torch.cuda.synchronize()
+    gna, gnr, gst = r.n_acc.cpu().numpy(), r.n_rej.cpu().numpy(), r.status.cpu().numpy()
+    assert (gst == 0).all()
+    top = np.argsort(gna + gnr, kind="stable")[-8:]
+    idx = np.unique(np.concatenate([synth.sample_indices(phi.shape[0], 40, 7), top]))
+    M = O.Mech(path)
+    cur, hh = phi[idx].copy(), np.zeros(len(idx))
+    na, nr = np.zeros(len(idx), dtype=np.int64), np.zeros(len(idx), dtype=np.int64)
+    for _ in range(wl.n_steps):
+        cur, hh, a, b, st = M.integrate(cur, wl.dt, h_io=hh, n_threads=NCPU)
+        assert (st == 0).all()
+        na += a
+        nr += b
+    out = r.phi.cpu().numpy()
+    same = _compare(phi[idx], out[idx], cur, (gna[idx], gnr[idx]), (na, nr), frac_diff=0.05)
+    print("heavytail: %d/%d sampled cells with identical counts; substeps of the costliest %s"
+          % (same, len(idx), (gna + gnr)[top].tolist()))
+    assert np.abs(out[:, 2:].sum(axis=1) - 1.0).max() < 1e-11
+
+
 def _run(S, x, dt):
     r = S.integrate(x, dt)
     torch.cuda.synchronize()
