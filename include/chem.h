@@ -224,13 +224,32 @@ int chem_bin_order(chem_solver* s, int64_t n, const float* cost_dev, const float
 
 /* ---- autotuning --------------------------------------------------------- */
 
-/* Time the candidate launch shapes (cells per wave, waves per block, queue
- * chunk) on n_sample cells (device [n_sample][2+Ns]) for the solver's current
- * schedule and keep the fastest in the solver's options. Synchronises.
- * Results are unaffected (the arithmetic per cell is the same for all
- * shapes). */
+/* Time the candidate launch shapes on n_sample cells (device
+ * [n_sample][2+Ns]) for the solver's current schedule and keep the fastest in
+ * the solver's options. Candidates: every compiled cells-per-wave variant,
+ * 1, 2 or 4 waves per block (as far as the LDS allows), and queue chunks 1,
+ * 2, 4, ..., 64 for the persistent schedules. Blocks per compute unit follow
+ * from the LDS footprint and are not searched. Synchronises. Results are
+ * unaffected (the arithmetic per cell is the same for all shapes). The load
+ * balancing this serves is the paper's (Methodology: load balancing of the
+ * chemistry problems); the search is this library's. */
 int chem_autotune(chem_solver* s, int64_t n_sample, const double* phi_sample_dev, double dt,
                   void* stream);
+
+/* chem_autotune through a cache file (host path, JSON lines, one object per
+ * tuned configuration:
+ *   {"key": "...", "cells_per_wave": c, "waves_per_block": w,
+ *    "queue_chunk": q, "ms": t}).
+ * The key names the mechanism (FNV-1a 64 of its packed image), the state
+ * size, the schedule, n_sample, dt, the device architecture and its
+ * compute-unit count. If a line with this key holds a shape the solver can
+ * run, the last such line sets the solver's options with nothing timed and
+ * *from_cache = 1. Otherwise the shapes are timed as by chem_autotune, the
+ * fastest is kept and appended to the file (created if missing), and
+ * *from_cache = 0. Lines that do not parse are skipped. Errors: CHEM_EINVAL
+ * for bad arguments or a file that cannot be written. */
+int chem_autotune_cached(chem_solver* s, const char* cache_path, int64_t n_sample, const double* phi_sample_dev,
+                         double dt, void* stream, int32_t* from_cache);
 
 /* Workspace of the workgroup-per-cell path (state sizes above 64): number of
  * HBM slots (cells in flight; one per resident workgroup, at most

@@ -87,6 +87,7 @@ def lib():
             "chem_bin_edges": (i32, [_vp, i64, _vp, _vp, _vp]),
             "chem_bin_order": (i32, [_vp, i64, _vp, _vp, _vp, _vp]),
             "chem_autotune": (i32, [_vp, i64, _vp, dbl, _vp]),
+            "chem_autotune_cached": (i32, [_vp, ctypes.c_char_p, i64, _vp, dbl, _vp, ctypes.POINTER(i32)]),
             "chem_workspace_info": (i32, [_vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
             "chem_kernel_timing": (i32, [_vp, i32]),
             "chem_kernel_times": (i32, [_vp, _vp, i32, ctypes.POINTER(i32)]),
@@ -386,7 +387,15 @@ class Solver:
         _check(lib().chem_kernel_times(self._h, a.ctypes.data_as(_vp), cap, ctypes.byref(n)))
         return a[:n.value].astype(np.float64)
 
-    def autotune(self, phi_sample: torch.Tensor, dt: float):
-        _check(lib().chem_autotune(self._h, phi_sample.shape[0],
-                                   _ptr(phi_sample, torch.float64, self.device, name="phi"), float(dt),
-                                   _stream(self.device)))
+    def autotune(self, phi_sample: torch.Tensor, dt: float, cache: Optional[str] = None) -> bool:
+        """Pick the fastest launch shape on phi_sample; with a cache path, read
+        it from / append it to that JSON-lines file. Returns True when the
+        shape came from the cache."""
+        p = _ptr(phi_sample, torch.float64, self.device, name="phi")
+        if cache is None:
+            _check(lib().chem_autotune(self._h, phi_sample.shape[0], p, float(dt), _stream(self.device)))
+            return False
+        hit = ctypes.c_int32()
+        _check(lib().chem_autotune_cached(self._h, os.fsencode(cache), phi_sample.shape[0], p, float(dt),
+                                          _stream(self.device), ctypes.byref(hit)))
+        return bool(hit.value)

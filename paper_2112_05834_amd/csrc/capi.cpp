@@ -63,6 +63,8 @@ constexpr size_t kMaxLds = 160 * 1024;
 struct chem_solver {
   int dev = 0;
   int cus = 0;
+  std::string arch;                  // device architecture name
+  unsigned long long mech_fp = 0;    // FNV-1a 64 of the packed mechanism image
   chem_opts opts{};
   int ns = 0, nr = 0, n = 0;
   chemk::MechArgs margs{};
@@ -109,6 +111,16 @@ struct chem_solver {
   float* log_target = nullptr;
   int64_t log_cap = 0;
 };
+
+constexpr unsigned long long kFnvBasis = 0xcbf29ce484222325ull;
+unsigned long long fnv1a(const void* p, size_t n, unsigned long long h) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
 
 extern "C" {
 
@@ -199,7 +211,11 @@ int chem_solver_create(const chem_mech* m, const chem_opts* o, int32_t dev, chem
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
   s->cus = prop.multiProcessorCount;
+  s->arch = prop.gcnArchName;
   const chem::Packed& P = m->packed;
+  s->mech_fp = fnv1a(P.blob.data(), P.blob.size(), kFnvBasis);
+  s->mech_fp = fnv1a(P.nasa.data(), P.nasa.size() * sizeof(double), s->mech_fp);
+  s->mech_fp = fnv1a(P.W.data(), P.W.size() * sizeof(double), s->mech_fp);
   HIP_TRY(hipMalloc(&s->d_blob, P.blob.size()), "hipMalloc");
   HIP_TRY(hipMemcpy(s->d_blob, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice), "hipMemcpy");
   HIP_TRY(hipMalloc(&s->d_nasa, P.nasa.size() * sizeof(double)), "hipMalloc");
@@ -789,26 +805,33 @@ int chem_bin_order(chem_solver* s, int64_t n, const float* cost, const float* ed
 
 // ---- autotuning ------------------------------------------------------------
 
-int chem_autotune(chem_solver* s, int64_t n_sample, const double* phi, double dt, void* stream) {
-  if (!s || n_sample < 1 || !phi || !(dt > 0)) return fail(CHEM_EINVAL, "chem_autotune: bad argument");
-  DeviceGuard g(s->dev);
-  hipStream_t st = static_cast<hipStream_t>(stream);
+}  // extern "C"
+
+// Time every launch shape (compiled cells-per-wave variants, 1/2/4 waves per
+// block, queue chunks 1..64 for the persistent schedules) on n_sample cells
+// and return the fastest in best.
+static int tune(chem_solver* s, int64_t n_sample, const double* phi, double dt, hipStream_t st, chem_opts& best,
+                float& best_ms) {
   if (int rc = ensure_ws(s)) return rc;
   const size_t w = static_cast<size_t>(s->ns) + 2;
   double* out = nullptr;
   double* h = nullptr;
   HIP_TRY(hipMalloc(&out, n_sample * w * sizeof(double)), "hipMalloc");
-  HIP_TRY(hipMalloc(&h, n_sample * sizeof(double)), "hipMalloc");
+  if (hipMalloc(&h, n_sample * sizeof(double)) != hipSuccess) {
+    hipFree(out);
+    return fail(CHEM_ENOMEM, "hipMalloc");
+  }
   hipEvent_t e0, e1;
   hipEventCreate(&e0);
   hipEventCreate(&e1);
-  chem_opts best = s->opts;
-  float best_ms = 1e30f;
+  best = s->opts;
+  best_ms = 1e30f;
   int rc = CHEM_OK;
-  const int chunks[] = {1, 2, 4, 8};
+  const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
+  const int nchunks = s->opts.schedule == CHEM_PLAIN ? 1 : 7;
   for (int vi = 0; vi < s->nvariants && rc == CHEM_OK; ++vi) {
     for (int wpb = 1; wpb <= 4 && rc == CHEM_OK; wpb *= 2) {
-      for (int ci = 0; ci < (s->opts.schedule == CHEM_PLAIN ? 1 : 4) && rc == CHEM_OK; ++ci) {
+      for (int ci = 0; ci < nchunks && rc == CHEM_OK; ++ci) {
         chem_opts o = s->opts;
         o.cells_per_wave = 64 / s->variants[vi].g;
         o.waves_per_block = wpb;
@@ -839,10 +862,89 @@ int chem_autotune(chem_solver* s, int64_t n_sample, const double* phi, double dt
   hipEventDestroy(e1);
   hipFree(out);
   hipFree(h);
-  if (rc) return rc;
   best.blocks = s->opts.blocks;
+  return rc;
+}
+
+static std::string tune_key(const chem_solver* s, int64_t n_sample, double dt) {
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "mech=%016llx n=%d schedule=%d sample=%lld dt=%.17g arch=%s cus=%d", s->mech_fp,
+                s->n, s->opts.schedule, static_cast<long long>(n_sample), dt, s->arch.c_str(), s->cus);
+  return buf;
+}
+
+// Integer value of "name": in a JSON line, or false.
+static bool json_int(const std::string& line, const char* name, long long& v) {
+  const std::string pat = std::string("\"") + name + "\":";
+  const size_t p = line.find(pat);
+  if (p == std::string::npos) return false;
+  const char* c = line.c_str() + p + pat.size();
+  char* e = nullptr;
+  v = std::strtoll(c, &e, 10);
+  return e != c;
+}
+
+extern "C" {
+
+int chem_autotune(chem_solver* s, int64_t n_sample, const double* phi, double dt, void* stream) {
+  if (!s || n_sample < 1 || !phi || !(dt > 0)) return fail(CHEM_EINVAL, "chem_autotune: bad argument");
+  DeviceGuard g(s->dev);
+  chem_opts best;
+  float ms = 0;
+  if (int rc = tune(s, n_sample, phi, dt, static_cast<hipStream_t>(stream), best, ms)) return rc;
   s->opts = best;
   drop_graph(s);
+  return CHEM_OK;
+}
+
+int chem_autotune_cached(chem_solver* s, const char* cache_path, int64_t n_sample, const double* phi, double dt,
+                         void* stream, int32_t* from_cache) {
+  if (!s || !cache_path || !from_cache || n_sample < 1 || !phi || !(dt > 0))
+    return fail(CHEM_EINVAL, "chem_autotune_cached: bad argument");
+  *from_cache = 0;
+  DeviceGuard g(s->dev);
+  const std::string key = tune_key(s, n_sample, dt);
+  const std::string kfield = "\"key\": \"" + key + "\"";
+  if (FILE* f = std::fopen(cache_path, "r")) {
+    std::string line;
+    char buf[1024];
+    bool hit = false;
+    chem_opts o = s->opts;
+    while (std::fgets(buf, sizeof(buf), f)) {
+      line = buf;
+      if (line.find(kfield) == std::string::npos) continue;
+      long long cpw, wpb, chunk;
+      if (!json_int(line, "cells_per_wave", cpw) || !json_int(line, "waves_per_block", wpb) ||
+          !json_int(line, "queue_chunk", chunk))
+        continue;
+      chem_opts t = s->opts;
+      t.cells_per_wave = static_cast<int32_t>(cpw);
+      t.waves_per_block = static_cast<int32_t>(wpb);
+      t.queue_chunk = static_cast<int32_t>(chunk);
+      Shape sh;
+      if (chunk < 1 || chunk > 1 << 20 || pick_shape(s, t, sh) != CHEM_OK) continue;
+      o = t;   // the last valid line for the key wins
+      hit = true;
+    }
+    std::fclose(f);
+    if (hit) {
+      s->opts = o;
+      drop_graph(s);
+      *from_cache = 1;
+      return CHEM_OK;
+    }
+  }
+  chem_opts best;
+  float ms = 0;
+  if (int rc = tune(s, n_sample, phi, dt, static_cast<hipStream_t>(stream), best, ms)) return rc;
+  s->opts = best;
+  drop_graph(s);
+  FILE* f = std::fopen(cache_path, "a");
+  if (!f) return fail(CHEM_EINVAL, std::string("chem_autotune_cached: cannot append to ") + cache_path);
+  std::fprintf(f, "{%s, \"cells_per_wave\": %d, \"waves_per_block\": %d, \"queue_chunk\": %d, \"ms\": %.4f}\n",
+               kfield.c_str(), best.cells_per_wave, best.waves_per_block, best.queue_chunk, ms);
+  const bool ok = std::fclose(f) == 0;
+  if (!ok) return fail(CHEM_EINVAL, std::string("chem_autotune_cached: write to ") + cache_path + " failed");
   return CHEM_OK;
 }
 

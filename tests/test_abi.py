@@ -69,6 +69,8 @@ def test_null_and_bad_arguments_are_errors_not_crashes():
     assert L.chem_bin_order(None, 1, None, None, None, None) == -1
     n = ctypes.c_int32()
     assert L.chem_kernel_times(None, None, 0, ctypes.byref(n)) == -1
+    assert L.chem_autotune(None, 1, None, 1e-6, None) == -1
+    assert L.chem_autotune_cached(None, b"/tmp/x.jsonl", 1, None, 1e-6, None, ctypes.byref(n)) == -1
     assert L.chem_last_error()          # a message is set
     L.chem_mech_free(None)               # NULL-safe
     L.chem_solver_free(None)
