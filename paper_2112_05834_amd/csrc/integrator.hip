@@ -140,7 +140,8 @@ struct Grp {
 // Per-cell LDS area layout (doubles): J [NN*NN] row-major, pivot-row buffer
 // P [NN+1 rounded to even], per-reaction buffers RB [5*nr] (rate of progress,
 // and with the Jacobian kf*theta, kr*theta, q0*dtheta/d[M], dq/dT), then the
-// per-species vectors C, gRT, hRT [ns each].
+// per-species vectors C, gRT, hRT [NN-1 each; entries from ns on are zero,
+// so column loops run to NN-1 without a bound check].
 struct CellArea {
   double* J;
   double* P;
@@ -152,7 +153,7 @@ struct CellArea {
 
 __host__ __device__ constexpr int pbuf_doubles(int nn) { return (nn + 2) & ~1; }
 __host__ __device__ constexpr int cell_doubles_c(int nn, int nr, int ns) {
-  return ((nn * nn + 1) & ~1) + pbuf_doubles(nn) + 5 * nr + 3 * ns;
+  return ((nn * nn + 1) & ~1) + pbuf_doubles(nn) + 5 * nr + 3 * (nn - 1);
 }
 
 template <int NN>
@@ -162,8 +163,8 @@ __device__ __forceinline__ CellArea cell_area(double* base, int nr, int ns) {
   c.P = base + ((NN * NN + 1) & ~1);
   c.RB = c.P + pbuf_doubles(NN);
   c.C = c.RB + 5 * nr;
-  c.gRT = c.C + ns;
-  c.hRT = c.gRT + ns;
+  c.gRT = c.C + (NN - 1);
+  c.hRT = c.gRT + (NN - 1);
   return c;
 }
 
@@ -257,6 +258,7 @@ struct Cell {
     const double Wbar = 1.0 / invWbar;
     const double rho = p * Wbar / (kR * T);
     const double Cs = rho * Ys * rWs;
+    const bool pad = i > ns && i < NN;      // padding component of a padded state size
     if (sp) ca.C[s] = Cs;
     const double Ctot = Gp::sum(Cs);
     // species thermo (NASA-7, range by T < Tmid)
@@ -266,6 +268,10 @@ struct Cell {
       nasa7<JAC>(A.nasa + 16 * s, T, rT, lnT, cpR, hRT, gRT, dcpR);
       ca.gRT[s] = gRT;
       ca.hRT[s] = hRT;
+    } else if (pad) {
+      ca.C[i - 1] = 0.0;
+      ca.gRT[i - 1] = 0.0;
+      ca.hRT[i - 1] = 0.0;
     }
     const double cp = Gp::sum(Ys * cpR * kR * rWs);
     double dcp = 0.0;
@@ -365,12 +371,13 @@ struct Cell {
     if (sp) {
       const double* Jrow = ca.J + i * NN + 1;
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      // columns from ns on are zero in J and in C
 #pragma unroll
       for (int k = 0; k < NN - 1; k += 4) {
-        if (k < ns) a0 = fma(Jrow[k], ca.C[k], a0);
-        if (k + 1 < ns && k + 1 < NN - 1) a1 = fma(Jrow[k + 1], ca.C[k + 1], a1);
-        if (k + 2 < ns && k + 2 < NN - 1) a2 = fma(Jrow[k + 2], ca.C[k + 2], a2);
-        if (k + 3 < ns && k + 3 < NN - 1) a3 = fma(Jrow[k + 3], ca.C[k + 3], a3);
+        a0 = fma(Jrow[k], ca.C[k], a0);
+        if (k + 1 < NN - 1) a1 = fma(Jrow[k + 1], ca.C[k + 1], a1);
+        if (k + 2 < NN - 1) a2 = fma(Jrow[k + 2], ca.C[k + 2], a2);
+        if (k + 3 < NN - 1) a3 = fma(Jrow[k + 3], ca.C[k + 3], a3);
       }
       sv = ((a0 + a1) + (a2 + a3)) + td * Ctot;
     }
@@ -381,12 +388,13 @@ struct Cell {
     double JT = 0.0;
     if (sp) {
       double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+      // rows beyond species ns - 1 are zero in J and in hRT
 #pragma unroll
       for (int q = 0; q < NN - 1; q += 4) {
-        if (q < ns) c0 = fma(ca.hRT[q], ca.J[(1 + q) * NN + i], c0);
-        if (q + 1 < ns && q + 1 < NN - 1) c1 = fma(ca.hRT[q + 1], ca.J[(2 + q) * NN + i], c1);
-        if (q + 2 < ns && q + 2 < NN - 1) c2 = fma(ca.hRT[q + 2], ca.J[(3 + q) * NN + i], c2);
-        if (q + 3 < ns && q + 3 < NN - 1) c3 = fma(ca.hRT[q + 3], ca.J[(4 + q) * NN + i], c3);
+        c0 = fma(ca.hRT[q], ca.J[(1 + q) * NN + i], c0);
+        if (q + 1 < NN - 1) c1 = fma(ca.hRT[q + 1], ca.J[(2 + q) * NN + i], c1);
+        if (q + 2 < NN - 1) c2 = fma(ca.hRT[q + 2], ca.J[(3 + q) * NN + i], c2);
+        if (q + 3 < NN - 1) c3 = fma(ca.hRT[q + 3], ca.J[(4 + q) * NN + i], c3);
       }
       const double cs = (c0 + c1) + (c2 + c3);
       const double dQdY = kR * T * ((rho * rWs) * (cs + HT) - (Wbar * rWs) * HS);
@@ -397,14 +405,14 @@ struct Cell {
     if (sp) {
       double* Jrow = ca.J + i * NN;
       const double Wi_rho = A.W[s] / rho;
+      // rW is zero from ns on (up to 64 entries), which keeps the padding
+      // columns of J zero
 #pragma unroll
       for (int k = 0; k < NN - 1; ++k) {
-        if (k < ns) {
-          const double rWk = L.rW[k];
-          const double D = Jrow[1 + k] + td;
-          const double dw = (rho * rWk) * D - (Wbar * rWk) * sv;
-          Jrow[1 + k] = Wi_rho * dw + fY * Wbar * rWk;
-        }
+        const double rWk = L.rW[k];
+        const double D = Jrow[1 + k] + td;
+        const double dw = (rho * rWk) * D - (Wbar * rWk) * sv;
+        Jrow[1 + k] = Wi_rho * dw + fY * Wbar * rWk;
       }
       Jrow[0] = Wi_rho * (wT - sv / T) + fY / T;
       ca.J[i] = JT;

@@ -284,7 +284,9 @@ Packed pack(const MechHost& m) {
   P.off_eff_sp = place(2 * eff_sp.size());
   P.off_sp_off = place(2 * sp_off.size());
   P.off_sp_ent = place(2 * sp_ent.size());
-  P.off_rW = place(8 * ns);
+  // rW is zero-padded to 64 entries, so that loops over the columns of a
+  // padded state size may read it without a bound check
+  P.off_rW = place(8 * std::max(ns, 64));
   P.lds_bytes = static_cast<int>(align16(off));
   P.off_lnA = place(8 * nr);
   P.off_b = place(8 * nr);
