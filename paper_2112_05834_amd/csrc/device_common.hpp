@@ -115,6 +115,33 @@ __device__ __forceinline__ void mass_action(const double* C, unsigned spw, unsig
   dP[2] = pw[0] * pw[1] * dp[2];
 }
 
+// Efficiency lists are read in chunks of kEffChunk entries whose loads are
+// all issued together (one LDS round trip per chunk rather than two per
+// entry); entries past the end read the list's first entry and are not used.
+constexpr int kEffChunk = 8;
+
+// Third-body concentration [M] = Ctot + sum_e (alpha_e - 1) C[sp_e], summed
+// in list order.
+__device__ __forceinline__ double third_body(const MechLds& L, const double* C, double Ctot, int eoff, int neff) {
+  double M = Ctot;
+  for (int e0 = 0; e0 < neff; e0 += kEffChunk) {
+    int sp[kEffChunk];
+    double am[kEffChunk], c[kEffChunk];
+#pragma unroll
+    for (int q = 0; q < kEffChunk; ++q) {
+      const int e = e0 + q < neff ? eoff + e0 + q : eoff;
+      sp[q] = L.eff_sp[e];
+      am[q] = L.eff_am1[e];
+    }
+#pragma unroll
+    for (int q = 0; q < kEffChunk; ++q) c[q] = C[sp[q]];
+#pragma unroll
+    for (int q = 0; q < kEffChunk; ++q)
+      if (e0 + q < neff) M = M + am[q] * c[q];
+  }
+  return M;
+}
+
 // Rate of progress of reaction rx from the cell's concentrations C and
 // species g/RT, h/RT: RB[rx] = theta q0 with q0 = kf prod C^nu' - kr prod
 // C^nu'' (kr = kf/Kc, Kc = exp(-sum nu g/RT) (p_atm/RT)^sum nu), theta = 1,
@@ -178,7 +205,7 @@ __device__ __forceinline__ void reaction_rate(const MechLds& L, const double* C,
   if (type >= 1) {
     double M = Ctot;
     const int eoff = w.w & 0xffff, neff = (w.w >> 16) & 0xff;
-    for (int e = 0; e < neff; ++e) M = M + L.eff_am1[eoff + e] * C[L.eff_sp[eoff + e]];
+    M = third_body(L, C, M, eoff, neff);
     if (type == 1) {
       theta = M;
       beta = 1.0;

@@ -216,12 +216,24 @@ __device__ __forceinline__ void jac_scatter(const MechLds& L, const double* C, c
   if (type >= 1) {
     const double q0b = RB[3 * nr + rx];
     const int eoff = w.w & 0xffff, neff = (w.w >> 16) & 0xff;
+    for (int e0 = 0; e0 < neff; e0 += kEffChunk) {
+      int sp[kEffChunk];
+      double am[kEffChunk];
 #pragma unroll
-    for (int a = 0; a < 6; ++a) {
-      if (!cv[a]) continue;
-      double* Jr = J + (1 + row[a]) * NN + 1;
-      const double ab = nu[a] * q0b;
-      for (int q = 0; q < neff; ++q) lds_add(&Jr[L.eff_sp[eoff + q]], ab * L.eff_am1[eoff + q]);
+      for (int q = 0; q < kEffChunk; ++q) {
+        const int e = e0 + q < neff ? eoff + e0 + q : eoff;
+        sp[q] = L.eff_sp[e];
+        am[q] = L.eff_am1[e];
+      }
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        if (!cv[a]) continue;
+        double* Jr = J + (1 + row[a]) * NN + 1;
+        const double ab = nu[a] * q0b;
+#pragma unroll
+        for (int q = 0; q < kEffChunk; ++q)
+          if (e0 + q < neff) lds_add(&Jr[sp[q]], ab * am[q]);
+      }
     }
   }
 }
