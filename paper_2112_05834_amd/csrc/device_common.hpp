@@ -148,11 +148,16 @@ __device__ __forceinline__ double third_body(const MechLds& L, const double* C, 
 // [M] or the Troe falloff factor. With JAC also RB[nr+rx] = kf theta,
 // RB[2nr+rx] = kr theta, RB[3nr+rx] = q0 dtheta/d[M] (times k0/kinf for
 // falloff) and RB[4nr+rx] = dq/dT at fixed C.
-template <bool JAC>
-__device__ __forceinline__ void reaction_rate(const MechLds& L, const double* C, const double* gRT, const double* hRT,
-                                              double* RB, int nr, int rx, double T, double rT, double lnT,
-                                              double lnRTp, double Ctot) {
-  const uint4 w = L.rint[rx];
+struct RateOut {
+  double q, kfT, krT, q0b, dqdT;
+};
+
+// (w is the reaction's packed word L.rint[rx]; with STORE the values are
+// also written to RB, else only returned)
+template <bool JAC, bool STORE = true>
+__device__ __forceinline__ RateOut reaction_rate(const MechLds& L, const uint4 w, const double* C, const double* gRT,
+                                                 const double* hRT, double* RB, int nr, int rx, double T, double rT,
+                                                 double lnT, double lnRTp, double Ctot) {
   const int type = (w.x >> 28) & 3;
   const bool rev = (w.x >> 30) & 1;
   const int nre = (w.x >> 24) & 0xf, npr = (w.y >> 24) & 0xf;
@@ -249,14 +254,31 @@ __device__ __forceinline__ void reaction_rate(const MechLds& L, const double* C,
       }
     }
   }
-  RB[rx] = theta * q0;
+  RateOut o{theta * q0, 0.0, 0.0, 0.0, 0.0};
   if (JAC) {
     const double dlnkr = rev ? dlnkf - (sumh * rT - dnu * rT) : 0.0;
-    RB[nr + rx] = kf * theta;
-    RB[2 * nr + rx] = kr * theta;
-    RB[3 * nr + rx] = q0 * beta;
-    RB[4 * nr + rx] = theta * (kf * dlnkf * Pf - kr * dlnkr * Pr) + q0 * dthdT;
+    o.kfT = kf * theta;
+    o.krT = kr * theta;
+    o.q0b = q0 * beta;
+    o.dqdT = theta * (kf * dlnkf * Pf - kr * dlnkr * Pr) + q0 * dthdT;
   }
+  if (STORE) {
+    RB[rx] = o.q;
+    if (JAC) {
+      RB[nr + rx] = o.kfT;
+      RB[2 * nr + rx] = o.krT;
+      RB[3 * nr + rx] = o.q0b;
+      RB[4 * nr + rx] = o.dqdT;
+    }
+  }
+  return o;
+}
+
+template <bool JAC, bool STORE = true>
+__device__ __forceinline__ RateOut reaction_rate(const MechLds& L, const double* C, const double* gRT,
+                                                 const double* hRT, double* RB, int nr, int rx, double T, double rT,
+                                                 double lnT, double lnRTp, double Ctot) {
+  return reaction_rate<JAC, STORE>(L, L.rint[rx], C, gRT, hRT, RB, nr, rx, T, rT, lnT, lnRTp, Ctot);
 }
 
 }  // namespace dev

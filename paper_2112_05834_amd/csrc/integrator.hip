@@ -138,10 +138,13 @@ struct Grp {
 };
 
 // Per-cell LDS area layout (doubles): J [NN*NN] row-major, pivot-row buffer
-// P [NN+1 rounded to even], per-reaction buffers RB [5*nr] (rate of progress,
-// and with the Jacobian kf*theta, kr*theta, q0*dtheta/d[M], dq/dT), then the
-// per-species vectors C, gRT, hRT [NN-1 each; entries from ns on are zero,
-// so column loops run to NN-1 without a bound check].
+// P [NN+1 rounded to even], a reaction/species buffer RB [max(5*nr, 3*NN)],
+// then the per-species vectors C, gRT, hRT [NN-1 each; entries from ns on
+// are zero, so column loops run to NN-1 without a bound check]. RB holds,
+// for state sizes up to 32, the per-reaction rate of progress (and with the
+// Jacobian kf*theta, kr*theta, q0*dtheta/d[M], dq/dT) read by the species
+// pass; above 32 it holds the species sums omega, d omega/dT and
+// sum nu q0 dtheta/d[M] [NN each] that the reaction lanes add into.
 struct CellArea {
   double* J;
   double* P;
@@ -152,8 +155,9 @@ struct CellArea {
 };
 
 __host__ __device__ constexpr int pbuf_doubles(int nn) { return (nn + 2) & ~1; }
+__host__ __device__ constexpr int rbuf_doubles(int nn, int nr) { return 5 * nr > 3 * nn ? 5 * nr : 3 * nn; }
 __host__ __device__ constexpr int cell_doubles_c(int nn, int nr, int ns) {
-  return ((nn * nn + 1) & ~1) + pbuf_doubles(nn) + 5 * nr + 3 * (nn - 1);
+  return ((nn * nn + 1) & ~1) + pbuf_doubles(nn) + rbuf_doubles(nn, nr) + 3 * (nn - 1);
 }
 
 template <int NN>
@@ -162,47 +166,62 @@ __device__ __forceinline__ CellArea cell_area(double* base, int nr, int ns) {
   c.J = base;
   c.P = base + ((NN * NN + 1) & ~1);
   c.RB = c.P + pbuf_doubles(NN);
-  c.C = c.RB + 5 * nr;
+  c.C = c.RB + rbuf_doubles(NN, nr);
   c.gRT = c.C + (NN - 1);
   c.hRT = c.gRT + (NN - 1);
   return c;
 }
 
-// Reaction-major Jacobian assembly (state sizes above 32, one cell per
-// wave): the lane of reaction rx forms its concentration partials once,
-// dq/dC_j = kf theta dPf_j for reactants and -kr theta dPr_j for products,
-// and adds nu_i dq/dC_j to J(1+i, 1+j) for every species i and j of the
-// reaction (nu_i = -order on the reactant side, +order on the product side),
-// plus nu_i (alpha_k - 1) q0 dtheta/d[M] for the listed third-body
-// efficiencies. LDS adds that return nothing; the lane-to-reaction mapping
-// is fixed, so the order of the adds into each element is fixed.
-template <int NN>
-__device__ __forceinline__ void jac_scatter(const MechLds& L, const double* C, const double* RB, int nr, int rx,
-                                            double* J) {
-  const uint4 w = L.rint[rx];
+// Reaction-major assembly (state sizes above 32, one cell per wave): the
+// lane of reaction rx adds nu_i q to om[i], and with the Jacobian nu_i dq/dT
+// to wT[i] and nu_i q0 dtheta/d[M] to td[i], for every species i of the
+// reaction (nu_i = -order on the reactant side, +order on the product side,
+// so a species on both sides gets two adds). With the Jacobian it also forms
+// the concentration partials once, dq/dC_j = kf theta dPf_j for reactants
+// and -kr theta dPr_j for products, and adds nu_i dq/dC_j to J(1+i, 1+j) for
+// every species i and j of the reaction, plus nu_i (alpha_k - 1) q0
+// dtheta/d[M] for the listed third-body efficiencies. LDS adds that return
+// nothing; the lane-to-reaction mapping is fixed, so the order of the adds
+// into each element is fixed.
+template <int NN, bool JAC>
+__device__ __forceinline__ void rx_scatter(const MechLds& L, const double* C, const uint4 w, const RateOut& r,
+                                           double* om, double* wT, double* td, double* J) {
   const int nre = (w.x >> 24) & 0xf, npr = (w.y >> 24) & 0xf;
+  const int type = (w.x >> 28) & 3;
+  double nu[6];
+  int row[6];
+  bool cv[6];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    cv[j] = j < nre;
+    cv[3 + j] = j < npr;
+    row[j] = cv[j] ? (w.x >> (8 * j)) & 0xff : 0;
+    row[3 + j] = cv[3 + j] ? (w.y >> (8 * j)) & 0xff : 0;
+    nu[j] = -static_cast<double>((w.z >> (4 * j)) & 0xf);
+    nu[3 + j] = static_cast<double>((w.z >> (12 + 4 * j)) & 0xf);
+  }
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    if (!cv[a]) continue;
+    lds_add(&om[row[a]], nu[a] * r.q);
+    if (JAC) {
+      lds_add(&wT[row[a]], nu[a] * r.dqdT);
+      if (type >= 1) lds_add(&td[row[a]], nu[a] * r.q0b);
+    }
+  }
+  if (!JAC) return;
   double Pf, Pr, dPf[3], dPr[3];
   int sf[3], sr[3];
   mass_action(C, w.x, w.z, nre, Pf, dPf, sf);
   mass_action(C, w.y, w.z >> 12, npr, Pr, dPr, sr);
-  const double kfT = RB[nr + rx], krT = RB[2 * nr + rx];
   double dq[6];
   int col[6];
-  bool cv[6];
-  double nu[6];
-  int row[6];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    dq[j] = kfT * dPf[j];
-    dq[3 + j] = -(krT * dPr[j]);
+    dq[j] = r.kfT * dPf[j];
+    dq[3 + j] = -(r.krT * dPr[j]);
     col[j] = sf[j];
     col[3 + j] = sr[j];
-    cv[j] = j < nre;
-    cv[3 + j] = j < npr;
-    nu[j] = -static_cast<double>((w.z >> (4 * j)) & 0xf);
-    nu[3 + j] = static_cast<double>((w.z >> (12 + 4 * j)) & 0xf);
-    row[j] = sf[j];
-    row[3 + j] = sr[j];
   }
 #pragma unroll
   for (int a = 0; a < 6; ++a) {
@@ -212,9 +231,7 @@ __device__ __forceinline__ void jac_scatter(const MechLds& L, const double* C, c
     for (int b = 0; b < 6; ++b)
       if (cv[b]) lds_add(&Jr[col[b]], nu[a] * dq[b]);
   }
-  const int type = (w.x >> 28) & 3;
   if (type >= 1) {
-    const double q0b = RB[3 * nr + rx];
     const int eoff = w.w & 0xffff, neff = (w.w >> 16) & 0xff;
     for (int e0 = 0; e0 < neff; e0 += kEffChunk) {
       int sp[kEffChunk];
@@ -229,7 +246,7 @@ __device__ __forceinline__ void jac_scatter(const MechLds& L, const double* C, c
       for (int a = 0; a < 6; ++a) {
         if (!cv[a]) continue;
         double* Jr = J + (1 + row[a]) * NN + 1;
-        const double ab = nu[a] * q0b;
+        const double ab = nu[a] * r.q0b;
 #pragma unroll
         for (int q = 0; q < kEffChunk; ++q)
           if (e0 + q < neff) lds_add(&Jr[sp[q]], ab * am[q]);
@@ -245,10 +262,10 @@ template <int NN, int G>
 struct Cell {
   static_assert(G >= NN, "one state component per lane");
   using Gp = Grp<G>;
-  // Reaction-major Jacobian assembly for state sizes above 32 (only 64-lane
-  // groups exist there); smaller sizes, which also run several cells per
-  // wave, keep the species-major assembly, whose order of additions does
-  // not depend on the group width.
+  // Reaction-major assembly of the production rates and the Jacobian for
+  // state sizes above 32 (only 64-lane groups exist there); smaller sizes,
+  // which also run several cells per wave, keep the species-major passes,
+  // whose order of additions does not depend on the group width.
   static constexpr bool kScatter = NN > 32;
 
   // f = dy/dt at y (this lane's component); with JAC also the analytical
@@ -294,6 +311,17 @@ struct Cell {
         for (int j = 0; j < NN; ++j) ca.J[i * NN + j] = 0.0;
       }
     }
+    // species sums of the reaction-major assembly
+    double* const som = ca.RB;
+    double* const swT = ca.RB + NN;
+    double* const std_ = ca.RB + 2 * NN;
+    if (kScatter && i < NN) {
+      som[i] = 0.0;
+      if (JAC) {
+        swT[i] = 0.0;
+        std_[i] = 0.0;
+      }
+    }
     wsync();
 
     // ---- reactions: one lane per reaction ----
@@ -301,8 +329,13 @@ struct Cell {
     for (int r0 = 0; r0 < nr; r0 += G) {
       const int rx = r0 + i;
       if (rx >= nr) break;
-      reaction_rate<JAC>(L, ca.C, ca.gRT, ca.hRT, ca.RB, nr, rx, T, rT, lnT, lnRTp, Ctot);
-      if constexpr (JAC && kScatter) jac_scatter<NN>(L, ca.C, ca.RB, nr, rx, ca.J);
+      if constexpr (kScatter) {
+        const uint4 w = L.rint[rx];
+        const RateOut r = reaction_rate<JAC, false>(L, w, ca.C, ca.gRT, ca.hRT, ca.RB, nr, rx, T, rT, lnT, lnRTp, Ctot);
+        rx_scatter<NN, JAC>(L, ca.C, w, r, som, swT, std_, ca.J);
+      } else {
+        reaction_rate<JAC>(L, ca.C, ca.gRT, ca.hRT, ca.RB, nr, rx, T, rT, lnT, lnRTp, Ctot);
+      }
     }
     wsync();
 
@@ -312,7 +345,15 @@ struct Cell {
     // the sum order is the program order); the next entry's records are
     // fetched before the current one is processed.
     double om = 0.0, wT = 0.0, td = 0.0;
-    if (sp) {
+    if (kScatter) {
+      if (sp) {
+        om = som[s];
+        if (JAC) {
+          wT = swT[s];
+          td = std_[s];
+        }
+      }
+    } else if (sp) {
       const int e0 = L.sp_off[s], e1 = L.sp_off[s + 1];
       double* Jrow = ca.J + i * NN + 1;
       if (!JAC) {
@@ -321,18 +362,6 @@ struct Cell {
           const unsigned ent = L.sp_ent[e];
           const double nu = static_cast<double>(static_cast<int>(ent >> 12) - 8);
           om = om + nu * ca.RB[ent & 0xfff];
-        }
-      } else if (kScatter) {
-        // the Jacobian rows were assembled reaction by reaction; q0 dtheta/d[M]
-        // is zero for elementary reactions
-#pragma unroll 4
-        for (int e = e0; e < e1; ++e) {
-          const unsigned ent = L.sp_ent[e];
-          const int rx = ent & 0xfff;
-          const double nu = static_cast<double>(static_cast<int>(ent >> 12) - 8);
-          om = om + nu * ca.RB[rx];
-          wT = wT + nu * ca.RB[4 * nr + rx];
-          td = td + nu * ca.RB[3 * nr + rx];
         }
       } else {
         unsigned ent = e0 < e1 ? L.sp_ent[e0] : 0u;
