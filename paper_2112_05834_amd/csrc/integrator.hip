@@ -542,15 +542,20 @@ struct Cell {
   __device__ static __forceinline__ double solve(const double (&M)[NN], int pos, double rdiag, double b) {
     const int i = Gp::gl();
     b = permute_d(b, 4 * (Gp::base() + (pos < NN ? pos : i)));
+    // the multipliers are masked rather than the update, which keeps the
+    // selects off the chain of dependent broadcasts (a zero multiplier
+    // leaves b unchanged for finite z)
 #pragma unroll
     for (int j = 0; j < NN - 1; ++j) {
+      const double lm = i > j ? M[j] : 0.0;
       const double z = Gp::bcast(b, j);
-      if (i > j) b = fma(-M[j], z, b);
+      b = fma(-lm, z, b);
     }
 #pragma unroll
     for (int j = NN - 1; j > 0; --j) {
+      const double um = i < j ? M[j] : 0.0;
       const double z = Gp::bcast(b * rdiag, j);
-      if (i < j) b = fma(-M[j], z, b);
+      b = fma(-um, z, b);
     }
     return b * rdiag;
   }
