@@ -152,13 +152,17 @@ struct RateOut {
   double q, kfT, krT, q0b, dqdT;
 };
 
-// (w is the reaction's packed word L.rint[rx]; with STORE the values are
-// also written to RB, else only returned)
-template <bool JAC, bool STORE = true>
-__device__ __forceinline__ RateOut reaction_rate(const MechLds& L, const uint4 w, const double* C, const double* gRT,
-                                                 const double* hRT, double* RB, int nr, int rx, double T, double rT,
-                                                 double lnT, double lnRTp, double Ctot) {
-  const int type = (w.x >> 28) & 3;
+// Rate evaluation in two parts, so that a caller can interleave two
+// reactions: rate_core forms kf, kr and the mass-action products (w is the
+// reaction's packed word L.rint[rx]); rate_finish applies the third-body or
+// falloff factor and forms the outputs (with STORE also written to RB).
+struct RateCore {
+  double kf, kr, Pf, Pr, q0, dlnkf, sumh;
+};
+
+template <bool JAC>
+__device__ __forceinline__ RateCore rate_core(const MechLds& L, const uint4 w, const double* C, const double* gRT,
+                                              const double* hRT, int rx, double rT, double lnT, double lnRTp) {
   const bool rev = (w.x >> 30) & 1;
   const int nre = (w.x >> 24) & 0xf, npr = (w.y >> 24) & 0xf;
   const int dnu = static_cast<int>((w.z >> 24) & 0x7f) - 64;
@@ -205,8 +209,19 @@ __device__ __forceinline__ RateOut reaction_rate(const MechLds& L, const uint4 w
   // kr = kf / Kc with Kc = exp(-sum nu g/RT) (p_atm/RT)^(sum nu)
   const double kr = rev ? exp(lnkf + sumg + dnu * lnRTp) : 0.0;
   const double q0 = kf * Pf - kr * Pr;
-  double theta = 1.0, beta = 0.0, dthdT = 0.0;
   const double dlnkf = (bb + ear * rT) * rT;
+  return RateCore{kf, kr, Pf, Pr, q0, dlnkf, sumh};
+}
+
+template <bool JAC, bool STORE = true>
+__device__ __forceinline__ RateOut rate_finish(const MechLds& L, const uint4 w, const RateCore& rc, const double* C,
+                                               double* RB, int nr, int rx, double T, double rT, double lnT,
+                                               double Ctot) {
+  const int type = (w.x >> 28) & 3;
+  const bool rev = (w.x >> 30) & 1;
+  const int dnu = static_cast<int>((w.z >> 24) & 0x7f) - 64;
+  const double kf = rc.kf, kr = rc.kr, Pf = rc.Pf, Pr = rc.Pr, q0 = rc.q0, dlnkf = rc.dlnkf, sumh = rc.sumh;
+  double theta = 1.0, beta = 0.0, dthdT = 0.0;
   if (type >= 1) {
     double M = Ctot;
     const int eoff = w.w & 0xffff, neff = (w.w >> 16) & 0xff;
@@ -272,6 +287,14 @@ __device__ __forceinline__ RateOut reaction_rate(const MechLds& L, const uint4 w
     }
   }
   return o;
+}
+
+template <bool JAC, bool STORE = true>
+__device__ __forceinline__ RateOut reaction_rate(const MechLds& L, const uint4 w, const double* C, const double* gRT,
+                                                 const double* hRT, double* RB, int nr, int rx, double T, double rT,
+                                                 double lnT, double lnRTp, double Ctot) {
+  const RateCore rc = rate_core<JAC>(L, w, C, gRT, hRT, rx, rT, lnT, lnRTp);
+  return rate_finish<JAC, STORE>(L, w, rc, C, RB, nr, rx, T, rT, lnT, Ctot);
 }
 
 template <bool JAC, bool STORE = true>

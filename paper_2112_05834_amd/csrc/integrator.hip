@@ -326,14 +326,35 @@ struct Cell {
 
     // ---- reactions: one lane per reaction ----
     const double lnRTp = log(kR * T / kPatm);
-    for (int r0 = 0; r0 < nr; r0 += G) {
-      const int rx = r0 + i;
-      if (rx >= nr) break;
-      if constexpr (kScatter) {
+    if constexpr (kScatter) {
+      // two blocks of reactions per pass, their rate evaluations interleaved
+      // (independent work for the one wave on the SIMD); the adds follow in
+      // block order
+      int r0 = 0;
+      for (; r0 + G < nr; r0 += 2 * G) {
+        const int rxa = r0 + i;
+        const int rxb = rxa + G;
+        const bool vb = rxb < nr;
+        const int rxb_c = vb ? rxb : rxa;
+        const uint4 wa = L.rint[rxa];
+        const uint4 wb = L.rint[rxb_c];
+        const RateCore ka = rate_core<JAC>(L, wa, ca.C, ca.gRT, ca.hRT, rxa, rT, lnT, lnRTp);
+        const RateCore kb = rate_core<JAC>(L, wb, ca.C, ca.gRT, ca.hRT, rxb_c, rT, lnT, lnRTp);
+        const RateOut ra = rate_finish<JAC, false>(L, wa, ka, ca.C, ca.RB, nr, rxa, T, rT, lnT, Ctot);
+        const RateOut rb = rate_finish<JAC, false>(L, wb, kb, ca.C, ca.RB, nr, rxb_c, T, rT, lnT, Ctot);
+        rx_scatter<NN, JAC>(L, ca.C, wa, ra, som, swT, std_, ca.J);
+        if (vb) rx_scatter<NN, JAC>(L, ca.C, wb, rb, som, swT, std_, ca.J);
+      }
+      if (r0 < nr && r0 + i < nr) {
+        const int rx = r0 + i;
         const uint4 w = L.rint[rx];
         const RateOut r = reaction_rate<JAC, false>(L, w, ca.C, ca.gRT, ca.hRT, ca.RB, nr, rx, T, rT, lnT, lnRTp, Ctot);
         rx_scatter<NN, JAC>(L, ca.C, w, r, som, swT, std_, ca.J);
-      } else {
+      }
+    } else {
+      for (int r0 = 0; r0 < nr; r0 += G) {
+        const int rx = r0 + i;
+        if (rx >= nr) break;
         reaction_rate<JAC>(L, ca.C, ca.gRT, ca.hRT, ca.RB, nr, rx, T, rT, lnT, lnRTp, Ctot);
       }
     }
