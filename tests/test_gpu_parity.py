@@ -280,3 +280,27 @@ def test_edge_cases(tiny):
     rc = chem.lib().chem_integrate(S._h, 4, 1e-6, chem.ctypes.c_void_p(y.data_ptr()),
                                    chem.ctypes.c_void_p(y[1:].data_ptr()), None, None, None, None, None)
     assert rc == -1    # partial overlap of phi_in and phi_out
+
+
+def test_kernel_timing_and_workspace_info(tiny, spray):
+    """Launch timing records one positive duration per integration launch made
+    outside graph capture (none inside), clears on read, and stops when
+    disabled; the per-wave path reports no HBM workspace."""
+    wl, mech, path, phi = spray
+    S = chem.Solver(chem.Mechanism(path), chem.default_opts(schedule=chem.PERSISTENT), device=0)
+    assert S.workspace_info() == (0, 0)
+    x = _to(phi[:2048])
+    S.kernel_timing(True)
+    for _ in range(3):
+        S.integrate(x, wl.dt, h_io=False)
+    t = S.kernel_times()
+    assert len(t) == 3 and (t > 0).all() and (t < 60e3).all()
+    assert len(S.kernel_times()) == 0
+    out = torch.empty_like(x)
+    S.integrate_steps(x, wl.dt, 2, h_io=False, out=out)       # captured: not recorded
+    torch.cuda.synchronize()
+    assert len(S.kernel_times()) == 0
+    S.kernel_timing(False)
+    S.integrate(x, wl.dt, h_io=False)
+    torch.cuda.synchronize()
+    assert len(S.kernel_times()) == 0

@@ -189,3 +189,19 @@ def test_wide_edge_cases(large):
     r = S.integrate_steps(xs, wl.dt, 2, h_io=False, out=out)
     torch.cuda.synchronize()
     assert torch.equal(r.phi, seq)
+
+
+def test_wide_workspace_info_and_timing(large):
+    wl, mech, path, phi = large
+    S = chem.Solver(chem.Mechanism(path), chem.default_opts(schedule=chem.PERSISTENT), device=0)
+    n = mech.n_species + 1
+    slots, per = S.workspace_info()
+    assert per == 2 * n * ((n + 15) // 16 * 16) * 8
+    assert slots >= 1
+    S.set_opts(chem.default_opts(schedule=chem.PERSISTENT, hbm_budget_bytes=2 * per + 1))
+    assert S.workspace_info() == (2, per)
+    S.kernel_timing(True)
+    S.integrate(_to(phi[:8]), wl.dt, h_io=False)
+    t = S.kernel_times()
+    S.kernel_timing(False)
+    assert len(t) == 1 and t[0] > 0
