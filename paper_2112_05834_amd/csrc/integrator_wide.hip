@@ -87,8 +87,8 @@ __device__ inline Wide wide_area(double* base, int ns, int nr, int ld) {
   return W;
 }
 
-// ---- workgroup reductions (fixed pairing: butterfly in the wave, then
-// waves (0+1)+(2+3)); every thread receives the same value ----
+// ---- workgroup sum (fixed pairing: butterfly in the wave, then waves
+// (0+1)+(2+3)); every thread receives the same value ----
 __device__ __forceinline__ double bsum(double v, double* red) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
@@ -96,36 +96,6 @@ __device__ __forceinline__ double bsum(double v, double* red) {
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   return (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-// index of the largest key, lowest index among equal keys
-__device__ __forceinline__ int bargmax(double key, int idx, double* red, int* ired) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const double ok = __shfl_xor(key, off);
-    const int oi = __shfl_xor(idx, off);
-    if (ok > key || (ok == key && oi < idx)) {
-      key = ok;
-      idx = oi;
-    }
-  }
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) {
-    red[8 + (threadIdx.x >> 6)] = key;
-    ired[threadIdx.x >> 6] = idx;
-  }
-  __syncthreads();
-  double bk = red[8];
-  int bi = ired[0];
-  for (int w = 1; w < 4; ++w) {
-    const double k2 = red[8 + w];
-    const int i2 = ired[w];
-    if (k2 > bk || (k2 == bk && i2 < bi)) {
-      bk = k2;
-      bi = i2;
-    }
-  }
-  return bi;
 }
 
 // ---- right-hand side and analytical Jacobian ----------------------------------
