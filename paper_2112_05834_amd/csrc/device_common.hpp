@@ -143,11 +143,12 @@ __device__ __forceinline__ double third_body(const MechLds& L, const double* C, 
 }
 
 // Rate of progress of reaction rx from the cell's concentrations C and
-// species g/RT, h/RT: RB[rx] = theta q0 with q0 = kf prod C^nu' - kr prod
-// C^nu'' (kr = kf/Kc, Kc = exp(-sum nu g/RT) (p_atm/RT)^sum nu), theta = 1,
-// [M] or the Troe falloff factor. With JAC also RB[nr+rx] = kf theta,
-// RB[2nr+rx] = kr theta, RB[3nr+rx] = q0 dtheta/d[M] (times k0/kinf for
-// falloff) and RB[4nr+rx] = dq/dT at fixed C.
+// species g/RT, h/RT: q = theta q0 with q0 = kf prod C^nu' - kr prod C^nu''
+// (kr = kf/Kc, Kc = exp(-sum nu g/RT) (p_atm/RT)^sum nu), theta = 1, [M] or
+// the Troe falloff factor. With JAC also kf theta, kr theta, q0 dtheta/d[M]
+// (times k0/kinf for falloff) and dq/dT at fixed C. Returned in RateOut and,
+// when stored, written to RB[rx], RB[nr+rx], RB[2nr+rx], RB[3nr+rx] and
+// RB[4nr+rx].
 struct RateOut {
   double q, kfT, krT, q0b, dqdT;
 };

@@ -364,10 +364,12 @@ struct Cell {
     wsync();
 
     // ---- species: production rates (and sparse Jacobian rows d omega/dC) ----
-    // The Jacobian row is accumulated with LDS adds that return nothing (the
-    // lane owns its row, and one wave's LDS operations execute in order, so
-    // the sum order is the program order); the next entry's records are
-    // fetched before the current one is processed.
+    // Above 32 state components the sums were formed by the reaction lanes
+    // and are read back. Otherwise each species lane walks its reactions'
+    // records; the Jacobian row is accumulated with LDS adds that return
+    // nothing (the lane owns its row, and one wave's LDS operations execute
+    // in order, so the sum order is the program order), and the next
+    // entry's records are fetched before the current one is processed.
     double om = 0.0, wT = 0.0, td = 0.0;
     if (kScatter) {
       if (sp) {
