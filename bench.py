@@ -161,6 +161,9 @@ def main():
     ap.add_argument("--chain", type=int, default=1, help="chemistry steps per graph launch (chained in a HIP graph)")
     ap.add_argument("--cells", type=int, default=0,
                     help="use only the first CELLS cells of the workload (profiling runs)")
+    ap.add_argument("--train-cells", type=int, default=0, metavar="N",
+                    help="log the cost model's training samples on the first N cells of each training seed "
+                         "(default: as many cells as the workload)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedules", default="plain,persistent,binned,truebins")
@@ -206,7 +209,7 @@ def main():
     training = None
     if "binned" in scheds or "truebins" in scheds:
         training = train_model(S, chem, torch, synth, wl, mech, TRAIN_SEEDS.get(args.workload, [1040, 1041]), log,
-                               n_cells)
+                               args.train_cells if args.train_cells > 0 else n_cells)
         log("model trained on %d samples: log %.1f s, train %.1f s, mse %.3f (target variance %.3f)" %
             (training["samples"], training["log_s"], training["train_s"], training["mse_ln_substeps"],
              training["target_var"]))
