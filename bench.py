@@ -73,6 +73,22 @@ def measured_traffic(kernel_src):
     return float(t.group(1)) * 1e6 if h.startswith(m.group(1)) else None
 
 
+def measured_fp64_ops(kernel_src):
+    """Executed FP64 operations per launch (all lanes) from the committed FP64
+    instruction-counter summary, if it was taken on the current kernel source
+    (else None)."""
+    path = os.path.join(ROOT, "profiles", "k_integrate_spray54_262144_fp64_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"sha256 prefix ([0-9a-f]+)", text)
+    t = re.search(r"executed FP64 operations: ([0-9.e+]+) per launch", text)
+    if not m or not t:
+        return None
+    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    return float(t.group(1)) if h.startswith(m.group(1)) else None
+
+
 def time_schedule(S, chem, torch, x, dt, steps, warmup, chain, **opts):
     """(last result, wall s, per-step event ms, per-launch kernel ms)."""
     S.set_opts(chem.default_opts(**opts))
@@ -268,9 +284,12 @@ def main():
     else:
         kern_s = float(np.mean(R["kms"])) / 1e3 if len(R["kms"]) else float(np.mean(R["ms"])) / 1e3
         achieved = flops / kern_s
-    traffic = measured_traffic(os.path.join(ROOT, "paper_2112_05834_amd", "csrc", "integrator.hip"))
+    src = os.path.join(ROOT, "paper_2112_05834_amd", "csrc", "integrator.hip")
+    traffic = measured_traffic(src)
+    executed = measured_fp64_ops(src)
     if args.workload != "spray54_262144" or args.chain > 1 or args.cells > 0:
         traffic = None
+        executed = None
     steps_total = args.steps * args.chain
     line = {
         "metric": METRIC,
@@ -293,7 +312,12 @@ def main():
                      "frac": None if achieved is None else achieved / FP64_VECTOR_PEAK,
                      "traffic": traffic,
                      "kernel": "k_integrate<%d,...> (%s schedule)" % (n, head),
-                     "flops_per_launch": flops, "kernel_ms": None if kern_s is None else kern_s * 1e3},
+                     "flops_per_launch": flops, "kernel_ms": None if kern_s is None else kern_s * 1e3,
+                     # FP64 operations the kernel executes (instruction counters, all lanes), beside
+                     # the algorithmic flops that `achieved` counts
+                     "executed": None if executed is None or kern_s is None else executed / kern_s / 1e12,
+                     "executed_frac": None if executed is None or kern_s is None else
+                     executed / kern_s / FP64_VECTOR_PEAK},
         "schedules": {k: {"cells_per_s": v["cells_per_s"], "ms_per_step": 1e3 * v["wall"] / steps_total,
                           "kernel_ms": float(np.mean(v["kms"])) if len(v["kms"]) else None,
                           "binning_used": v["used"]}
