@@ -821,9 +821,13 @@ static int tune(chem_solver* s, int64_t n_sample, const double* phi, double dt, 
     hipFree(out);
     return fail(CHEM_ENOMEM, "hipMalloc");
   }
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    hipFree(out);
+    hipFree(h);
+    return fail(CHEM_EHIP, "autotune: hipEventCreate failed");
+  }
   best = s->opts;
   best_ms = 1e30f;
   int rc = CHEM_OK;
