@@ -844,16 +844,18 @@ static int tune(chem_solver* s, int64_t n_sample, const double* phi, double dt, 
         if (pick_shape(s, o, sh) != CHEM_OK || sh.wpb != wpb) continue;
         float ms = 0;
         for (int rep = 0; rep < 2; ++rep) {   // first repetition warms up
-          hipMemsetAsync(h, 0, n_sample * sizeof(double), st);
-          hipEventRecord(e0, st);
+          if (hipMemsetAsync(h, 0, n_sample * sizeof(double), st) != hipSuccess ||
+              hipEventRecord(e0, st) != hipSuccess) {
+            rc = fail(CHEM_EHIP, "autotune: stream operation failed");
+            break;
+          }
           rc = launch_step(s, o, n_sample, dt, phi, out, h, nullptr, nullptr, nullptr, 0, nullptr, st);
-          hipEventRecord(e1, st);
           if (rc) break;
-          if (hipEventSynchronize(e1) != hipSuccess) {
+          if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
             rc = fail(CHEM_EHIP, "autotune: launch failed");
             break;
           }
-          hipEventElapsedTime(&ms, e0, e1);
         }
         if (rc == CHEM_OK && ms < best_ms) {
           best_ms = ms;
