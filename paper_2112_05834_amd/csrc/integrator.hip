@@ -537,7 +537,11 @@ struct Cell {
         if (info == 0) info = k + 1;
         rp = 0.0;
       } else {
-        rp = 1.0 / akk;
+        // hardware reciprocal refined by two Newton steps (a shorter
+        // dependent chain than a correctly rounded division)
+        rp = __builtin_amdgcn_rcp(akk);
+        rp = fma(rp, fma(-akk, rp, 1.0), rp);
+        rp = fma(rp, fma(-akk, rp, 1.0), rp);
       }
       if (is_owner) rdiag = rp;
       const bool below = pos > k && pos < NN;
