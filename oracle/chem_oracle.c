@@ -38,7 +38,8 @@ typedef struct {
 } orc_rxn;
 
 struct orc_mech {
-  int ns, nr;
+  int ns, nr, ne;
+  int* elem;       /* [ns][ne] atoms of each element per molecule */
   double* W;       /* [ns] kg/mol */
   double* trange;  /* [ns][3] Tlow Tmid Thigh */
   double* lo;      /* [ns][7] */
@@ -83,7 +84,7 @@ void orc_mech_free(orc_mech* m) {
   if (m->rx) {
     for (int r = 0; r < m->nr; ++r) { free(m->rx[r].eff_sp); free(m->rx[r].eff_a); }
   }
-  free(m->rx); free(m->W); free(m->trange); free(m->lo); free(m->hi);
+  free(m->rx); free(m->elem); free(m->W); free(m->trange); free(m->lo); free(m->hi);
   free(m);
 }
 
@@ -120,6 +121,8 @@ int orc_mech_load(const char* path, orc_mech** out) {
     if (tk_next(&t, &s) || tk_dbl(&t, &w)) PFAIL("element line");
   }
   if (tk_expect(&t, "species") || tk_int(&t, &m->ns) || m->ns < 1) PFAIL("species");
+  m->ne = ne;
+  m->elem = (int*)calloc((size_t)m->ns * ne, sizeof(int));
   m->W = (double*)calloc(m->ns, sizeof(double));
   m->trange = (double*)calloc(3 * m->ns, sizeof(double));
   m->lo = (double*)calloc(7 * m->ns, sizeof(double));
@@ -128,7 +131,10 @@ int orc_mech_load(const char* path, orc_mech** out) {
     const char* s; int c;
     if (tk_next(&t, &s) || tk_dbl(&t, &m->W[i])) PFAIL("species line");
     for (int k = 0; k < 3; ++k) if (tk_dbl(&t, &m->trange[3 * i + k])) PFAIL("T range");
-    for (int e = 0; e < ne; ++e) if (tk_int(&t, &c)) PFAIL("element count");
+    for (int e = 0; e < ne; ++e) {
+      if (tk_int(&t, &c) || c < 0) PFAIL("element count");
+      m->elem[i * ne + e] = c;
+    }
     for (int k = 0; k < 7; ++k) if (tk_dbl(&t, &m->lo[7 * i + k])) PFAIL("nasa lo");
     for (int k = 0; k < 7; ++k) if (tk_dbl(&t, &m->hi[7 * i + k])) PFAIL("nasa hi");
     if (!(m->W[i] > 0)) PFAIL("W <= 0");
@@ -776,5 +782,55 @@ int orc_integrate(const orc_mech* m, long n_cells, double dt, const orc_opts* o,
   for (int i = 0; i < n_threads; ++i) pthread_create(&th[i], NULL, worker, &jb);
   for (int i = 0; i < n_threads; ++i) pthread_join(th[i], NULL);
   free(th);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* mixture fraction (Methodology: zonal reference mapping)                   */
+/* ------------------------------------------------------------------------ */
+
+int orc_mech_elements(const orc_mech* m, int* ne, int* counts) {
+  if (!m) return -1;
+  if (ne) *ne = m->ne;
+  if (counts) memcpy(counts, m->elem, sizeof(int) * (size_t)m->ns * m->ne);
+  return 0;
+}
+
+/* Bilger's coupling function of one composition: moles of element e per kg of
+ * mixture are sum_i a_{e,i} Y_i / W_i, so
+ *   beta(Y) = sum_e coupling[e] sum_i a_{e,i} Y_i / W_i = sum_i Y_i b_i,
+ *   b_i = (sum_e coupling[e] a_{e,i}) / W_i.
+ * Sums run in natural index order, each term added by one fused multiply-add. */
+static double bilger_coef(const orc_mech* m, const double* coupling, int i) {
+  double s = 0.0;
+  for (int e = 0; e < m->ne; ++e) s = fma(coupling[e], (double)m->elem[i * m->ne + e], s);
+  return s / m->W[i];
+}
+
+static double bilger_beta(const orc_mech* m, const double* coupling, const double* Y) {
+  double beta = 0.0;
+  for (int i = 0; i < m->ns; ++i) beta = fma(Y[i], bilger_coef(m, coupling, i), beta);
+  return beta;
+}
+
+/* Z = (beta - beta_ox) / (beta_fuel - beta_ox): 0 in the oxidiser stream, 1 in
+ * the fuel stream, linear in Y in between (a conserved scalar when every
+ * reaction conserves the elements). Returns -1 if the two streams have the
+ * same beta. */
+int orc_mixture_fraction(const orc_mech* m, const double* coupling, const double* y_fuel,
+                         const double* y_ox, long n, const double* phi, double* z) {
+  if (!m || !coupling || !y_fuel || !y_ox || n < 0 || (n > 0 && (!phi || !z))) {
+    snprintf(g_err, sizeof g_err, "orc_mixture_fraction: bad argument");
+    return -1;
+  }
+  const double bf = bilger_beta(m, coupling, y_fuel);
+  const double bo = bilger_beta(m, coupling, y_ox);
+  if (!(bf != bo) || !isfinite(bf) || !isfinite(bo)) {
+    snprintf(g_err, sizeof g_err, "orc_mixture_fraction: fuel and oxidiser streams have the same beta");
+    return -1;
+  }
+  const int stride = m->ns + 2;
+  for (long c = 0; c < n; ++c)
+    z[c] = (bilger_beta(m, coupling, phi + c * stride + 2) - bo) / (bf - bo);
   return 0;
 }

@@ -88,6 +88,22 @@ int orc_integrate(const orc_mech* m, long n_cells, double dt, const orc_opts* o,
                   const double* phi_in, double* phi_out, double* h_io, int* n_acc, int* n_rej,
                   signed char* status, int n_threads);
 
+/* Zonal reference mapping (paper: Methodology, the DLBFoam paragraph): a cell
+ * is either integrated or takes the solution of a reference cell with a
+ * similar Bilger mixture fraction Z.
+ *
+ * orc_mech_elements: number of elements and, if counts is not NULL, the atom
+ * counts [ns][ne] of every species. Returns 0, or -1 for a NULL mechanism.
+ *
+ * orc_mixture_fraction: Z of n cells phi [n][2+Ns] into z [n]. coupling [ne]
+ * weighs the moles of each element per kg of mixture (Bilger: 2 for C, 1/2
+ * for H, -1 for O); y_fuel and y_ox [Ns] are the two stream compositions
+ * (Z = 1 and Z = 0). Returns 0, or -1 on a bad argument or if the streams have
+ * the same coupling value. */
+int orc_mech_elements(const orc_mech* m, int* n_elements, int* counts);
+int orc_mixture_fraction(const orc_mech* m, const double* coupling, const double* y_fuel,
+                         const double* y_ox, long n, const double* phi, double* z);
+
 #ifdef __cplusplus
 }
 #endif

@@ -62,6 +62,8 @@ def lib():
         L.orc_integrate.argtypes = [ctypes.c_void_p, ctypes.c_long, ctypes.c_double,
                                     ctypes.POINTER(_Opts), _dp, _dp, _dp, _ip, _ip,
                                     ctypes.POINTER(ctypes.c_byte), ctypes.c_int]
+        L.orc_mech_elements.argtypes = [ctypes.c_void_p, _ip, _ip]
+        L.orc_mixture_fraction.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, ctypes.c_long, _dp, _dp]
         _lib = L
     return _lib
 
@@ -148,6 +150,69 @@ class Mech:
         if rc != 0:
             raise ValueError(lib().orc_last_error().decode())
         return out, h, na, nr, st
+
+    def elements(self):
+        """Atom counts [Ns, Ne] of every species."""
+        ne = ctypes.c_int()
+        lib().orc_mech_elements(self._h, ctypes.byref(ne), None)
+        counts = np.zeros((self.ns, ne.value), dtype=np.int32)
+        lib().orc_mech_elements(self._h, ctypes.byref(ne), _i(counts))
+        return counts
+
+    def mixture_fraction(self, coupling, y_fuel, y_ox, phi):
+        """Bilger mixture fraction of every cell (paper: Methodology, zonal
+        reference mapping; the coupling function is Bilger's)."""
+        c = np.ascontiguousarray(coupling, dtype=np.float64)
+        yf = np.ascontiguousarray(y_fuel, dtype=np.float64)
+        yo = np.ascontiguousarray(y_ox, dtype=np.float64)
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        assert c.shape == (self.elements().shape[1],) and yf.shape == yo.shape == (self.ns,)
+        z = np.zeros(phi.shape[0])
+        if lib().orc_mixture_fraction(self._h, _d(c), _d(yf), _d(yo), phi.shape[0], _d(phi), _d(z)) != 0:
+            raise ValueError(lib().orc_last_error().decode())
+        return z
+
+    def integrate_zonal(self, phi, dt: float, coupling, y_fuel, y_ox, z_max: float, t_tol: float,
+                        h_io=None, **kw):
+        """Zonal reference mapping around the integrator (paper: Methodology,
+        the DLBFoam paragraph: a cell is either solved or mapped from a
+        reference solution of similar mixture fraction), read as:
+
+        - the zone is every cell with Z <= z_max; its reference is the zone
+          cell of lowest index;
+        - a zone cell other than the reference whose |T - T_ref| <= t_tol is
+          mapped: it takes the reference's change of state over dt,
+          T + (T_ref,out - T_ref,in) and Y_k + (Y_ref,out,k - Y_ref,in,k), with
+          p, h unchanged, no steps counted and the reference's status;
+        - every other cell is integrated as by :meth:`integrate`.
+
+        Returns (phi_out, h, n_acc, n_rej, status, mapped)."""
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        n = phi.shape[0]
+        z = self.mixture_fraction(coupling, y_fuel, y_ox, phi)
+        zone = np.nonzero(z <= z_max)[0]
+        mapped = np.zeros(n, dtype=bool)
+        ref = -1
+        if zone.size:
+            ref = int(zone[0])
+            for i in zone[1:]:
+                mapped[i] = abs(phi[i, 0] - phi[ref, 0]) <= t_tol
+        solve = np.nonzero(~mapped)[0]
+        out = phi.copy()
+        h = np.zeros(n) if h_io is None else np.array(h_io, dtype=np.float64)
+        na = np.zeros(n, dtype=np.int32)
+        nr = np.zeros(n, dtype=np.int32)
+        st = np.zeros(n, dtype=np.int8)
+        if solve.size:
+            o, hs, a, r, s = self.integrate(phi[solve], dt, h_io=h[solve], **kw)
+            out[solve], h[solve], na[solve], nr[solve], st[solve] = o, hs, a, r, s
+        for i in np.nonzero(mapped)[0]:
+            out[i, 0] = phi[i, 0] + (out[ref, 0] - phi[ref, 0])
+            out[i, 1] = phi[i, 1]
+            for k in range(2, phi.shape[1]):
+                out[i, k] = phi[i, k] + (out[ref, k] - phi[ref, k])
+            st[i] = st[ref]
+        return out, h, na, nr, st, mapped
 
 
 def lu(A):

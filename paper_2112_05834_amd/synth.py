@@ -424,7 +424,7 @@ class Workload:
     pressure: float
     dt: float
     state_seed: int
-    recipe: str           # "uniform" | "bimodal" | "heavytail"
+    recipe: str           # "uniform" | "bimodal" | "heavytail" | "ambient"
     n_steps: int = 1
 
 
@@ -434,7 +434,27 @@ WORKLOADS = {
     "spray54_heavytail_1048576": Workload("spray54_heavytail_1048576", "spray54", 1048576, 6.0e6,
                                           1e-6, 103, "heavytail", n_steps=10),
     "large160_524288": Workload("large160_524288", "large160", 524288, 4.0e6, 5e-7, 105, "bimodal"),
+    "spray54_ambient_262144": Workload("spray54_ambient_262144", "spray54", 262144, 6.0e6, 1e-6, 106,
+                                       "ambient"),
 }
+
+# Weights of the elements in Bilger's coupling function, per mole of atoms:
+# E0 is hydrogen-like (1/2), E1 carbon-like (2), E2 oxygen-like (-1), E3 the
+# inert nitrogen-like element (0).
+BILGER_COUPLING = (0.5, 2.0, -1.0, 0.0)
+
+
+def bilger_streams(mech: Mechanism):
+    """(coupling [Ne], y_fuel [Ns], y_ox [Ns]) for the mixture fraction of a
+    synthetic mechanism: the fuel stream is the pure fuel species, the
+    oxidiser stream the 0.23:0.77 oxidiser:inert mixture of the unburnt cells."""
+    ns = mech.n_species
+    yf = np.zeros(ns)
+    yf[mech.fuel] = 1.0
+    yo = np.zeros(ns)
+    yo[mech.oxidiser] = 0.23
+    yo[mech.inert] = 0.77
+    return np.array(BILGER_COUPLING[:mech.elem.shape[1]]), yf, yo
 
 
 def mech_cached(name: str, directory: str) -> Tuple[Mechanism, str]:
@@ -488,6 +508,10 @@ def generate_states(mech: Mechanism, n_cells: int, pressure: float, recipe: str,
                   0.23:0.77 oxidiser:inert), 30% hot products-rich cells
                   (T ~ N(2200, 150^2) K, 256 templates with 1% log-normal
                   composition noise and +-5 K)
+      ambient   - the bimodal recipe, then 60% of the cells replaced by
+                  ambient oxidiser-side gas (Spray A's hot ambient before
+                  the spray reaches it): oxidiser:inert 0.23:0.77 with the
+                  1e-12 floor of the unburnt cells, T = 900 K + U[-0.5, 0.5] K
       heavytail - T log-spaced over [700, 2600] K, composition blended
                   between unburnt and hot templates by (T-700)/1900; 5% of
                   the cells are ignition-front cells with T ~ U[1100, 1600] K
@@ -511,6 +535,15 @@ def generate_states(mech: Mechanism, n_cells: int, pressure: float, recipe: str,
         Y[hot] = _noisy(rng, tmpl[pick], 0.01)
         phi[:, 0] = T
         phi[:, 2:] = Y
+    elif recipe == "ambient":
+        phi = generate_states(mech, n_cells, pressure, "bimodal", seed)
+        amb = rng.uniform(size=n_cells) < 0.6
+        na = int(amb.sum())
+        Y = np.full(ns, 1e-12)
+        Y[mech.oxidiser] = 0.23
+        Y[mech.inert] = 0.77
+        phi[amb, 0] = 900.0 + rng.uniform(-0.5, 0.5, size=na)
+        phi[amb, 2:] = Y / Y.sum()
     elif recipe == "heavytail":
         T = np.exp(np.linspace(math.log(700.0), math.log(2600.0), n_cells))
         rng.shuffle(T)
