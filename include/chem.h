@@ -259,6 +259,51 @@ int chem_autotune_cached(chem_solver* s, const char* cache_path, int64_t n_sampl
  * no HBM workspace. */
 int chem_workspace_info(chem_solver* s, int32_t* slots, int64_t* bytes_per_slot);
 
+/* ---- zonal reference mapping ---------------------------------------- */
+/* Paper: Methodology, the DLBFoam paragraph. A cell is either integrated or
+ * takes the solution of a reference cell with a similar Bilger mixture
+ * fraction Z. Read here as:
+ *   beta(Y) = sum_i Y_i / W_i * sum_e coupling[e] a_{e,i}  (a = atom counts),
+ *   Z = (beta(Y) - beta(y_ox)) / (beta(y_fuel) - beta(y_ox));
+ * the zone is every cell with Z <= z_max, and its reference is the zone cell
+ * of lowest index. A zone cell whose |T - T_ref| <= t_tol is mapped: it takes
+ * the reference's change of T and of every Y over the step (p kept). */
+
+/* Number of elements of the mechanism and, if counts is not NULL, the atom
+ * counts of every species: host int32 [Ns][n_elements], row-major. */
+int chem_mech_elements(const chem_mech* m, int32_t* n_elements, int32_t* counts);
+
+/* Set the mixture-fraction definition and the mapping thresholds of a solver.
+ * coupling: host [n_elements], the weight of each element's moles per kg of
+ * mixture (Bilger: 2 for carbon, 1/2 for hydrogen, -1 for oxygen, 0 for the
+ * rest). y_fuel, y_ox: host [Ns], the stream compositions (Z = 1 and 0).
+ * z_max and t_tol [K] are compared with <=. Allocates the solver's zone
+ * buffers on first use and synchronises the device. Errors: CHEM_EINVAL (NULL
+ * or non-finite argument, t_tol < 0, or streams with the same beta),
+ * CHEM_EHIP. Do not call while a zonal integration of this solver is in
+ * flight. */
+int chem_zone_config(chem_solver* s, const double* coupling, const double* y_fuel, const double* y_ox,
+                     double z_max, double t_tol);
+
+/* Z of n cells: phi device [n][2+Ns] in, z device [n] FP64 out; enqueued on
+ * stream. Errors: CHEM_EINVAL, CHEM_ESTATE (no chem_zone_config yet). */
+int chem_mixture_fraction(chem_solver* s, int64_t n_cells, const double* phi, double* z, void* stream);
+
+/* chem_integrate with zonal reference mapping: same arrays and semantics as
+ * chem_integrate for the integrated cells. A mapped cell gets
+ * phi_out = phi_in + (reference's phi_out - phi_in) for T and Y, its p
+ * unchanged, n_acc = n_rej = 0, the reference's status, and its h_io left as
+ * it was. mapped: device int8 [n] out (1 mapped, 0 integrated), or NULL.
+ * The integrated cells always go through the persistent queue (learned
+ * binning is not applied to them). Enqueue only, no host synchronisation.
+ * The solver's zone buffers are shared by its calls: do not overlap two
+ * zonal calls of one solver on different streams. n_cells at most
+ * 2^31 - 1. Errors: as chem_integrate, plus CHEM_ESTATE (no
+ * chem_zone_config yet). */
+int chem_integrate_zonal(chem_solver* s, int64_t n_cells, double dt, const double* phi_in, double* phi_out,
+                         double* h_io, int32_t* n_acc, int32_t* n_rej, int8_t* status, int8_t* mapped,
+                         void* stream);
+
 /* ---- kernel timing ---------------------------------------------------- */
 
 /* enable != 0: from now on record a pair of HIP events on the caller's

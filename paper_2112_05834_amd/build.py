@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchem.so")
-SOURCES = ["mech.cpp", "capi.cpp", "integrator.hip", "integrator_wide.hip", "model.hip"]
+SOURCES = ["mech.cpp", "capi.cpp", "integrator.hip", "integrator_wide.hip", "model.hip", "zonal.hip"]
 ARCH = os.environ.get("CHEM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

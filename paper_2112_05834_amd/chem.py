@@ -91,6 +91,10 @@ def lib():
             "chem_workspace_info": (i32, [_vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
             "chem_kernel_timing": (i32, [_vp, i32]),
             "chem_kernel_times": (i32, [_vp, _vp, i32, ctypes.POINTER(i32)]),
+            "chem_mech_elements": (i32, [_vp, ctypes.POINTER(i32), _vp]),
+            "chem_zone_config": (i32, [_vp, _vp, _vp, _vp, dbl, dbl]),
+            "chem_mixture_fraction": (i32, [_vp, i64, _vp, _vp, _vp]),
+            "chem_integrate_zonal": (i32, [_vp, i64, dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "chem_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -153,6 +157,15 @@ class Mechanism:
         _check(lib().chem_mech_dims(h, ctypes.byref(ns), ctypes.byref(nr)))
         self.n_species, self.n_reactions = ns.value, nr.value
         self.n = self.n_species + 1
+
+    def elements(self):
+        """Atom counts [Ns, Ne] (numpy int32) of every species."""
+        import numpy as np
+        ne = ctypes.c_int32()
+        _check(lib().chem_mech_elements(self._h, ctypes.byref(ne), None))
+        counts = np.zeros((self.n_species, ne.value), dtype=np.int32)
+        _check(lib().chem_mech_elements(self._h, ctypes.byref(ne), counts.ctypes.data_as(_vp)))
+        return counts
 
     def work(self):
         v = [ctypes.c_double() for _ in range(4)]
@@ -232,6 +245,43 @@ class Solver:
                                     _ptr(h, torch.float64, self.device, n, "h_io"),
                                     _ptr(na), _ptr(nr), _ptr(st), _stream(self.device)))
         return Result(phi_out, h, na, nr, st)
+
+    # ---- zonal reference mapping ----
+    def zone_config(self, coupling, y_fuel, y_ox, z_max: float, t_tol: float):
+        """Mixture-fraction definition (host sequences: coupling per element,
+        fuel and oxidiser compositions per species) and mapping thresholds."""
+        import numpy as np
+        c = np.ascontiguousarray(coupling, dtype=np.float64)
+        yf = np.ascontiguousarray(y_fuel, dtype=np.float64)
+        yo = np.ascontiguousarray(y_ox, dtype=np.float64)
+        if c.shape != (self.mech.elements().shape[1],) or yf.shape != (self.ns,) or yo.shape != (self.ns,):
+            raise ValueError("coupling must be [n_elements], y_fuel and y_ox [n_species]")
+        _check(lib().chem_zone_config(self._h, c.ctypes.data_as(_vp), yf.ctypes.data_as(_vp),
+                                      yo.ctypes.data_as(_vp), float(z_max), float(t_tol)))
+
+    def mixture_fraction(self, phi: torch.Tensor) -> torch.Tensor:
+        n = phi.shape[0]
+        z = torch.empty(n, dtype=torch.float64, device=self.device)
+        _check(lib().chem_mixture_fraction(self._h, n, _ptr(phi, torch.float64, self.device,
+                                                            n * (self.ns + 2), "phi"),
+                                           _ptr(z), _stream(self.device)))
+        return z
+
+    def integrate_zonal(self, phi: torch.Tensor, dt: float, h_io: Optional[torch.Tensor] = None,
+                        out: Optional[torch.Tensor] = None):
+        """One chemistry step with zonal reference mapping: (Result, mapped),
+        mapped an int8 tensor (1 = took the reference's change of state)."""
+        n = phi.shape[0]
+        if phi.dim() != 2 or phi.shape[1] != self.ns + 2:
+            raise ValueError("phi must be [n, %d]" % (self.ns + 2))
+        phi_out, h, na, nr, st = self._outs(n, h_io, out)
+        mapped = torch.empty(n, dtype=torch.int8, device=self.device)
+        _check(lib().chem_integrate_zonal(self._h, n, float(dt),
+                                          _ptr(phi, torch.float64, self.device, n * (self.ns + 2), "phi"),
+                                          _ptr(phi_out, torch.float64, self.device, n * (self.ns + 2), "out"),
+                                          _ptr(h, torch.float64, self.device, n, "h_io"),
+                                          _ptr(na), _ptr(nr), _ptr(st), _ptr(mapped), _stream(self.device)))
+        return Result(phi_out, h, na, nr, st), mapped
 
     def integrate_steps(self, phi: torch.Tensor, dt: float, n_steps: int,
                         h_io: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None) -> Result:

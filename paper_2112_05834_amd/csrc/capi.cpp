@@ -16,6 +16,7 @@
 #include "kernels.hpp"
 #include "mech.hpp"
 #include "model.hpp"
+#include "zonal.hpp"
 
 struct chem_mech {
   chem::MechHost host;
@@ -110,6 +111,16 @@ struct chem_solver {
   float* log_feats = nullptr;
   float* log_target = nullptr;
   int64_t log_cap = 0;
+  // zonal reference mapping
+  int ne = 0;
+  std::vector<int> elem;              // [ns][ne] atom counts
+  bool zone_ready = false;
+  double z_max = 0, t_tol = 0;
+  double* d_zone = nullptr;           // coef [ns], streams [2], reference row [ns+2]
+  unsigned long long* d_zctl = nullptr;
+  signed char* d_zflag = nullptr;
+  int* d_zorder = nullptr;
+  int64_t zone_cap = 0;
 };
 
 constexpr unsigned long long kFnvBasis = 0xcbf29ce484222325ull;
@@ -197,6 +208,8 @@ int chem_solver_create(const chem_mech* m, const chem_opts* o, int32_t dev, chem
   s->nr = m->host.nr;
   s->n = s->ns + 1;
   s->work = m->work;
+  s->ne = m->host.ne;
+  s->elem = m->host.elem;
   s->nvariants = chemk::variants_for(s->n, s->variants, 8);
   if (s->nvariants == 0 && s->n <= chemk::kWideNN) {
     s->wide = true;
@@ -284,6 +297,10 @@ void chem_solver_free(chem_solver* s) {
   hipFree(s->d_ws);
   hipFree(s->log_feats);
   hipFree(s->log_target);
+  hipFree(s->d_zone);
+  hipFree(s->d_zctl);
+  hipFree(s->d_zflag);
+  hipFree(s->d_zorder);
   if (s->capture_stream) hipStreamDestroy(s->capture_stream);
   delete s;
 }
@@ -398,7 +415,7 @@ int ensure_ws(chem_solver* s) {
 // One chemistry step with the solver's options on stream st.
 int launch_step(chem_solver* s, const chem_opts& o, int64_t n, double dt, const double* in, double* out,
                 double* h_io, int32_t* n_acc, int32_t* n_rej, int8_t* status, int accumulate,
-                const int* perm, hipStream_t st) {
+                const int* perm, hipStream_t st, bool head_set = false) {
   Shape sh;
   if (int rc = pick_shape(s, o, sh)) return rc;
   chemk::IntegrateArgs a{};
@@ -435,7 +452,7 @@ int launch_step(chem_solver* s, const chem_opts& o, int64_t n, double dt, const 
     grid = s->wide_slots;
     if (o.blocks > 0 && o.blocks < grid) grid = o.blocks;
     if (grid > n) grid = n;
-    if (persistent) HIP_TRY(chemk::launch_fill_u64(s->d_head, 0ull, st), "queue reset");
+    if (persistent && !head_set) HIP_TRY(chemk::launch_fill_u64(s->d_head, 0ull, st), "queue reset");
   } else if (!persistent) {
     grid = (n + per_block - 1) / per_block;
   } else {
@@ -444,7 +461,7 @@ int launch_step(chem_solver* s, const chem_opts& o, int64_t n, double dt, const 
     grid = o.blocks > 0 ? o.blocks : static_cast<long long>(s->cus) * bpc;
     const long long need = (n + per_block - 1) / per_block;
     if (grid > need) grid = need;
-    HIP_TRY(chemk::launch_fill_u64(s->d_head, 0ull, st), "queue reset");
+    if (!head_set) HIP_TRY(chemk::launch_fill_u64(s->d_head, 0ull, st), "queue reset");
   }
   if (grid < 1) return CHEM_OK;
   if (grid > 0x7fffffffLL) return fail(CHEM_EINVAL, "too many cells for one launch");
@@ -991,6 +1008,125 @@ int chem_kernel_times(chem_solver* s, float* ms, int32_t cap, int32_t* n_out) {
   }
   clear_timing(s);
   *n_out = k;
+  return CHEM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// zonal reference mapping
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int chem_mech_elements(const chem_mech* m, int32_t* ne, int32_t* counts) {
+  if (!m || !ne) return fail(CHEM_EINVAL, "chem_mech_elements: null argument");
+  *ne = m->host.ne;
+  if (counts)
+    for (size_t i = 0; i < m->host.elem.size(); ++i) counts[i] = m->host.elem[i];
+  return CHEM_OK;
+}
+
+int chem_zone_config(chem_solver* s, const double* coupling, const double* y_fuel, const double* y_ox,
+                     double z_max, double t_tol) {
+  if (!s || !coupling || !y_fuel || !y_ox) return fail(CHEM_EINVAL, "chem_zone_config: null argument");
+  if (!std::isfinite(z_max) || !std::isfinite(t_tol) || t_tol < 0)
+    return fail(CHEM_EINVAL, "chem_zone_config: z_max and t_tol must be finite, t_tol >= 0");
+  for (int e = 0; e < s->ne; ++e)
+    if (!std::isfinite(coupling[e])) return fail(CHEM_EINVAL, "chem_zone_config: non-finite coupling");
+  for (int i = 0; i < s->ns; ++i)
+    if (!std::isfinite(y_fuel[i]) || !std::isfinite(y_ox[i]))
+      return fail(CHEM_EINVAL, "chem_zone_config: non-finite stream composition");
+  DeviceGuard g(s->dev);
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  const int ns = s->ns, ne = s->ne;
+  if (!s->d_zone) {
+    HIP_TRY(hipMalloc(&s->d_zone, sizeof(double) * (2 * ns + 4)), "hipMalloc zone");
+    HIP_TRY(hipMalloc(&s->d_zctl, 2 * sizeof(unsigned long long)), "hipMalloc zone");
+  }
+  // inputs staged in one temporary buffer: coupling, y_fuel, y_ox, counts
+  std::vector<double> in(ne + 2 * ns);
+  std::copy(coupling, coupling + ne, in.begin());
+  std::copy(y_fuel, y_fuel + ns, in.begin() + ne);
+  std::copy(y_ox, y_ox + ns, in.begin() + ne + ns);
+  void* d_in = nullptr;
+  const size_t in_bytes = sizeof(double) * in.size() + sizeof(int) * s->elem.size();
+  HIP_TRY(hipMalloc(&d_in, in_bytes), "hipMalloc zone inputs");
+  double* din = static_cast<double*>(d_in);
+  int* dcounts = reinterpret_cast<int*>(din + in.size());
+  hipError_t e = hipMemcpy(din, in.data(), sizeof(double) * in.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(dcounts, s->elem.data(), sizeof(int) * s->elem.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = chemz::launch_zone_setup(ns, ne, din, dcounts, s->d_W, din + ne, din + ne + ns, s->d_zone, s->d_zone + ns,
+                                 nullptr);
+  double streams[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpy(streams, s->d_zone + ns, sizeof(streams), hipMemcpyDeviceToHost);
+  hipFree(d_in);
+  if (e != hipSuccess) return hip_fail(e, "zone setup");
+  if (!(streams[0] != streams[1]) || !std::isfinite(streams[0]) || !std::isfinite(streams[1])) {
+    s->zone_ready = false;
+    return fail(CHEM_EINVAL, "chem_zone_config: fuel and oxidiser streams have the same coupling value");
+  }
+  s->z_max = z_max;
+  s->t_tol = t_tol;
+  s->zone_ready = true;
+  return CHEM_OK;
+}
+
+int chem_mixture_fraction(chem_solver* s, int64_t n, const double* phi, double* z, void* stream) {
+  if (!s) return fail(CHEM_EINVAL, "null solver");
+  if (n < 0 || (n > 0 && (!phi || !z))) return fail(CHEM_EINVAL, "chem_mixture_fraction: bad argument");
+  if (!s->zone_ready) return fail(CHEM_ESTATE, "chem_mixture_fraction: call chem_zone_config first");
+  DeviceGuard g(s->dev);
+  HIP_TRY(chemz::launch_mixture_fraction(n, s->ns, phi, s->d_zone, s->d_zone + s->ns, z,
+                                         static_cast<hipStream_t>(stream)),
+          "mixture fraction launch");
+  return CHEM_OK;
+}
+
+int chem_integrate_zonal(chem_solver* s, int64_t n, double dt, const double* in, double* out, double* h_io,
+                         int32_t* n_acc, int32_t* n_rej, int8_t* status, int8_t* mapped, void* stream) {
+  if (int rc = check_integrate_args(s, n, dt, in, out)) return rc;
+  if (!s->zone_ready) return fail(CHEM_ESTATE, "chem_integrate_zonal: call chem_zone_config first");
+  if (n > 0x7fffffffLL) return fail(CHEM_EINVAL, "chem_integrate_zonal: more than 2^31 - 1 cells");
+  if (n == 0) return CHEM_OK;
+  DeviceGuard g(s->dev);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int rc = ensure_ws(s)) return rc;
+  if (s->zone_cap < n) {
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    hipFree(s->d_zflag);
+    hipFree(s->d_zorder);
+    s->d_zflag = nullptr;
+    s->d_zorder = nullptr;
+    s->zone_cap = 0;
+    HIP_TRY(hipMalloc(&s->d_zflag, static_cast<size_t>(n)), "hipMalloc zone flags");
+    HIP_TRY(hipMalloc(&s->d_zorder, sizeof(int) * static_cast<size_t>(n)), "hipMalloc zone order");
+    s->zone_cap = n;
+  }
+  chemz::ZoneArgs z{};
+  z.n = n;
+  z.ns = s->ns;
+  z.phi_in = in;
+  z.phi_out = out;
+  z.coef = s->d_zone;
+  z.streams = s->d_zone + s->ns;
+  z.stash = s->d_zone + s->ns + 2;
+  z.z_max = s->z_max;
+  z.t_tol = s->t_tol;
+  z.flag = mapped ? reinterpret_cast<signed char*>(mapped) : s->d_zflag;
+  z.order = s->d_zorder;
+  z.ctl = s->d_zctl;
+  z.head = s->d_head;
+  z.n_acc = n_acc;
+  z.n_rej = n_rej;
+  z.status = reinterpret_cast<signed char*>(status);
+  HIP_TRY(chemz::launch_zone_classify(z, st), "zone classify launch");
+  HIP_TRY(chemz::launch_zone_select(z, st), "zone select launch");
+  chem_opts o = s->opts;
+  o.schedule = CHEM_PERSISTENT;
+  if (int rc = launch_step(s, o, n, dt, in, out, h_io, n_acc, n_rej, status, 0, s->d_zorder, st, true)) return rc;
+  HIP_TRY(chemz::launch_zone_apply(z, st), "zone apply launch");
   return CHEM_OK;
 }
 

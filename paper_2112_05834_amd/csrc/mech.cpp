@@ -92,6 +92,8 @@ bool parse_mechanism(const std::string& path, MechHost& m, std::string& err) {
   }
   if (!tk.word("species") || !tk.integer(m.ns) || m.ns < 1) return fail("bad species count");
   if (m.ns > kMaxSpecies) return fail("more than 255 species");
+  m.ne = ne;
+  m.elem.assign(static_cast<size_t>(m.ns) * ne, 0);
   m.W.resize(m.ns);
   m.tmid.resize(m.ns);
   m.lo.resize(7 * m.ns);
@@ -103,8 +105,10 @@ bool parse_mechanism(const std::string& path, MechHost& m, std::string& err) {
     if (!tk.next(name) || !tk.real(m.W[i]) || !tk.real(tl) || !tk.real(m.tmid[i]) || !tk.real(th))
       return fail("bad species line");
     if (!(m.W[i] > 0)) return fail("non-positive molecular weight");
-    for (int e = 0; e < ne; ++e)
-      if (!tk.integer(c)) return fail("bad element count");
+    for (int e = 0; e < ne; ++e) {
+      if (!tk.integer(c) || c < 0) return fail("bad element count");
+      m.elem[static_cast<size_t>(i) * ne + e] = c;
+    }
     for (int k = 0; k < 7; ++k)
       if (!tk.real(m.lo[7 * i + k])) return fail("bad NASA coefficient");
     for (int k = 0; k < 7; ++k)

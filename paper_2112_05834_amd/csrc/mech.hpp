@@ -22,7 +22,8 @@ struct Rxn {
 };
 
 struct MechHost {
-  int ns = 0, nr = 0;
+  int ns = 0, nr = 0, ne = 0;
+  std::vector<int> elem;                 // [ns][ne] atoms of each element per molecule
   std::vector<double> W;                 // kg/mol
   std::vector<double> tmid;              // NASA range boundary per species
   std::vector<double> lo, hi;            // [ns][7]

@@ -1,0 +1,174 @@
+// Zonal reference mapping around the integrator (paper: Methodology, the
+// DLBFoam paragraph), read as follows:
+// - Z is Bilger's mixture fraction, a linear function of the mass fractions:
+//     beta(Y) = sum_i Y_i b_i,  b_i = (sum_e coupling_e a_{e,i}) / W_i,
+//     Z = (beta - beta_ox) / (beta_fuel - beta_ox);
+// - the zone is every cell with Z <= z_max, and its reference is the zone cell
+//   of lowest index;
+// - a zone cell within t_tol of the reference's temperature is mapped: it
+//   takes the reference's change of T and Y over the step. Every other cell
+//   is integrated.
+//
+// All of this is streaming work next to the integration, so the kernels are
+// plain one-thread-per-cell (or per element) passes. Z is summed in natural
+// species order with one fused multiply-add per term, so that a cell's zone
+// decision does not depend on how the work is split.
+#include "zonal.hpp"
+
+namespace chemz {
+namespace {
+
+constexpr unsigned long long kNone = ~0ull;
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double beta_of(const double* Y, const double* coef, int ns) {
+  double b = 0.0;
+  for (int i = 0; i < ns; ++i) b = fma(Y[i], coef[i], b);
+  return b;
+}
+
+__device__ __forceinline__ double z_of(const double* Y, const double* coef, int ns, const double* streams) {
+  const double bf = streams[0], bo = streams[1];
+  return (beta_of(Y, coef, ns) - bo) / (bf - bo);
+}
+
+__global__ void k_zone_setup(int ns, int ne, const double* coupling, const int* counts, const double* W,
+                             const double* yf, const double* yo, double* coef, double* streams) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int i = 0; i < ns; ++i) {
+    double s = 0.0;
+    for (int e = 0; e < ne; ++e) s = fma(coupling[e], static_cast<double>(counts[i * ne + e]), s);
+    coef[i] = s / W[i];
+  }
+  streams[0] = beta_of(yf, coef, ns);
+  streams[1] = beta_of(yo, coef, ns);
+}
+
+__global__ void k_mixture_fraction(long long n, int ns, const double* phi, const double* coef,
+                                   const double* streams, double* z) {
+  const long long c = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x;
+  if (c < n) z[c] = z_of(phi + c * (ns + 2) + 2, coef, ns, streams);
+}
+
+__global__ void k_zone_reset(unsigned long long* ctl) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl[0] = kNone;
+    ctl[1] = 0;
+  }
+}
+
+// One atomic per wave: its lowest zone lane holds its lowest zone cell.
+__global__ void k_zone_classify(ZoneArgs a) {
+  const long long c = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x;
+  bool zone = false;
+  if (c < a.n) {
+    zone = z_of(a.phi_in + c * (a.ns + 2) + 2, a.coef, a.ns, a.streams) <= a.z_max;
+    a.flag[c] = zone ? 1 : 0;
+  }
+  const unsigned long long m = __ballot(zone);
+  if (m && static_cast<unsigned long long>(__lane_id()) == static_cast<unsigned long long>(__builtin_ctzll(m)))
+    atomicMin(a.ctl, static_cast<unsigned long long>(c));
+}
+
+// Mapped flags and the queue order of the integrated cells: each wave claims
+// a run of positions, counted down from the end of order, with one atomic.
+__global__ void k_zone_select(ZoneArgs a) {
+  const long long c = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x;
+  const int stride = a.ns + 2;
+  const unsigned long long ref = a.ctl[0];
+  bool mapped = false;
+  if (c < a.n) {
+    if (ref != kNone && a.flag[c] && static_cast<unsigned long long>(c) != ref)
+      mapped = fabs(a.phi_in[c * stride] - a.phi_in[static_cast<long long>(ref) * stride]) <= a.t_tol;
+    a.flag[c] = mapped ? 1 : 0;
+    if (static_cast<unsigned long long>(c) == ref)
+      for (int k = 0; k < stride; ++k) a.stash[k] = a.phi_in[c * stride + k];
+  }
+  const bool keep = c < a.n && !mapped;
+  const unsigned long long m = __ballot(keep);
+  const int lane = __lane_id();
+  unsigned long long base = 0;
+  if (lane == 0 && m) base = atomicAdd(a.ctl + 1, static_cast<unsigned long long>(__popcll(m)));
+  base = __shfl(base, 0);
+  if (keep) {
+    const unsigned long long k = base + static_cast<unsigned long long>(__popcll(m & ((1ull << lane) - 1ull)));
+    a.order[a.n - 1 - static_cast<long long>(k)] = static_cast<int>(c);
+  }
+}
+
+// The persistent kernel pulls queue positions from head up to n: start it at
+// the first integrated cell.
+__global__ void k_zone_head(long long n, const unsigned long long* ctl, unsigned long long* head) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) head[0] = static_cast<unsigned long long>(n) - ctl[1];
+}
+
+// One thread per element of a mapped cell's row: T and Y move by the
+// reference's change, p stays; no steps counted, the reference's status.
+__global__ void k_zone_apply(ZoneArgs a) {
+  const unsigned long long ref = a.ctl[0];
+  if (ref == kNone) return;
+  const int stride = a.ns + 2;
+  const long long total = a.n * stride;
+  const long long r0 = static_cast<long long>(ref) * stride;
+  for (long long e = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; e < total;
+       e += static_cast<long long>(gridDim.x) * blockDim.x) {
+    const long long c = e / stride;
+    if (!a.flag[c]) continue;
+    const int k = static_cast<int>(e - c * stride);
+    const double x = a.phi_in[e];
+    a.phi_out[e] = k == 1 ? x : x + (a.phi_out[r0 + k] - a.stash[k]);
+    if (k == 0) {
+      if (a.n_acc) a.n_acc[c] = 0;
+      if (a.n_rej) a.n_rej[c] = 0;
+      if (a.status) a.status[c] = a.status[ref];
+    }
+  }
+}
+
+unsigned grid_for(long long n) {
+  return static_cast<unsigned>((n + kThreads - 1) / kThreads);
+}
+
+}  // namespace
+
+hipError_t launch_zone_setup(int ns, int ne, const double* coupling, const int* counts, const double* W,
+                             const double* y_fuel, const double* y_ox, double* coef, double* streams,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_zone_setup, dim3(1), dim3(64), 0, st, ns, ne, coupling, counts, W, y_fuel, y_ox, coef,
+                     streams);
+  return hipGetLastError();
+}
+
+hipError_t launch_mixture_fraction(long long n, int ns, const double* phi, const double* coef,
+                                   const double* streams, double* z, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mixture_fraction, dim3(grid_for(n)), dim3(kThreads), 0, st, n, ns, phi, coef, streams, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_zone_classify(const ZoneArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_zone_reset, dim3(1), dim3(64), 0, st, a.ctl);
+  if (hipError_t e = hipGetLastError()) return e;
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zone_classify, dim3(grid_for(a.n)), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_zone_select(const ZoneArgs& a, hipStream_t st) {
+  if (a.n > 0) {
+    hipLaunchKernelGGL(k_zone_select, dim3(grid_for(a.n)), dim3(kThreads), 0, st, a);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  hipLaunchKernelGGL(k_zone_head, dim3(1), dim3(64), 0, st, a.n, a.ctl, a.head);
+  return hipGetLastError();
+}
+
+hipError_t launch_zone_apply(const ZoneArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  long long blocks = (a.n * (a.ns + 2) + kThreads - 1) / kThreads;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_zone_apply, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace chemz

@@ -71,9 +71,19 @@ def test_null_and_bad_arguments_are_errors_not_crashes():
     assert L.chem_kernel_times(None, None, 0, ctypes.byref(n)) == -1
     assert L.chem_autotune(None, 1, None, 1e-6, None) == -1
     assert L.chem_autotune_cached(None, b"/tmp/x.jsonl", 1, None, 1e-6, None, ctypes.byref(n)) == -1
+    assert L.chem_zone_config(None, None, None, None, 0.0, 0.0) == -1
+    assert L.chem_mixture_fraction(None, 1, None, None, None) == -1
+    assert L.chem_integrate_zonal(None, 1, 1e-6, None, None, None, None, None, None, None, None) == -1
+    assert L.chem_mech_elements(None, ctypes.byref(n), None) == -1
     assert L.chem_last_error()          # a message is set
     L.chem_mech_free(None)               # NULL-safe
     L.chem_solver_free(None)
+
+
+def test_element_counts_match_the_generator(tmp_path):
+    from paper_2112_05834_amd import chem, synth
+    mech, path = synth.mech_cached("spray54", str(tmp_path))
+    assert (chem.Mechanism(path).elements() == mech.elem).all()
 
 
 def test_too_many_species_is_a_mechanism_error(tmp_path):
