@@ -89,12 +89,15 @@ def measured_fp64_ops(kernel_src):
     return float(t.group(1)) if h.startswith(m.group(1)) else None
 
 
-def time_schedule(S, chem, torch, x, dt, steps, warmup, chain, **opts):
-    """(last result, wall s, per-step event ms, per-launch kernel ms)."""
+def time_schedule(S, chem, torch, x, dt, steps, warmup, chain, zonal=False, **opts):
+    """(last result, wall s, per-step event ms, per-launch kernel ms). zonal:
+    one step with zonal reference mapping (chem_integrate_zonal) per step."""
     S.set_opts(chem.default_opts(**opts))
     out = torch.empty_like(x)
 
     def one():
+        if zonal:
+            return S.integrate_zonal(x, dt, h_io=False, out=out)[0]
         if chain > 1:
             return S.integrate_steps(x, dt, chain, h_io=False, out=out)
         return S.integrate(x, dt, h_io=False, out=out)
@@ -182,7 +185,10 @@ def main():
                          "(default: as many cells as the workload)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--schedules", default="plain,persistent,binned,truebins")
+    ap.add_argument("--schedules", default="plain,persistent,binned,truebins",
+                    help="comma list of plain, persistent, binned, truebins, zonal")
+    ap.add_argument("--zone", default="1e-6,1.0", metavar="Z_MAX,T_TOL",
+                    help="zonal schedule: cells with Z <= Z_MAX within T_TOL kelvin of the reference are mapped")
     ap.add_argument("--autotune", type=int, default=0, metavar="CELLS",
                     help="pick launch shape and queue chunk by timing a seeded sample of this many cells first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -244,7 +250,12 @@ def main():
         log("autotuned on %d cells: %s" % (len(idx), tuned))
 
     codes = {"plain": chem.PLAIN, "persistent": chem.PERSISTENT, "binned": chem.PERSISTENT_BINNED,
-             "truebins": chem.PERSISTENT_BINNED}
+             "truebins": chem.PERSISTENT_BINNED, "zonal": chem.PERSISTENT}
+    if "zonal" in scheds:
+        if args.chain > 1:
+            raise SystemExit("the zonal schedule runs one chemistry step per call (--chain 1)")
+        z_max, t_tol = (float(v) for v in args.zone.split(","))
+        S.zone_config(*synth.bilger_streams(mech), z_max, t_tol)
     results = {}
     true_cost = None
     for sched in scheds:
@@ -260,7 +271,7 @@ def main():
             extra = {"waves_per_block": tuned["waves_per_block"], "queue_chunk": tuned["queue_chunk"],
                      "cells_per_wave": tuned["cells_per_wave"]}
         r, wall, ms, kms = time_schedule(S, chem, torch, x, wl.dt, args.steps, args.warmup, args.chain,
-                                         schedule=codes[sched], **extra)
+                                         zonal=sched == "zonal", schedule=codes[sched], **extra)
         used = S.last_binning_used() if codes[sched] == chem.PERSISTENT_BINNED else None
         if sched == "truebins":
             S.set_cost_override(None)
@@ -270,6 +281,13 @@ def main():
         cells = n_cells * args.steps * args.chain
         results[sched] = dict(wall=wall, ms=ms, kms=kms, na=na, nr=nr, status=stt, used=used,
                               cells_per_s=cells / wall)
+        if "zonal" in scheds and sched in ("zonal", "persistent"):
+            results[sched]["T"] = r.phi[:, 0].cpu().numpy()
+        if sched == "zonal":
+            mapped = S.integrate_zonal(x, wl.dt, h_io=False)[1].cpu().numpy().astype(bool)
+            results[sched]["mapped"] = mapped
+            log("zonal: %.1f%% of the cells mapped (Z <= %g, |T - T_ref| <= %g K)" %
+                (100 * mapped.mean(), z_max, t_tol))
         log("%s %.1f ms/step (events %s), kernel ms %s, %.4e cells/s, failed cells %d, binning used %s" %
             (sched, 1e3 * wall / (args.steps * args.chain), ["%.1f" % m for m in ms],
              ["%.1f" % m for m in kms[:4]], cells / wall, int((stt != 0).sum()), used))
@@ -340,6 +358,16 @@ def main():
                                      "frac": fp64["frac"], "flops_per_launch": flops}}
     if "plain" in results and head != "plain":
         line["speedup_vs_plain"] = R["cells_per_s"] / results["plain"]["cells_per_s"]
+    if "zonal" in results:
+        Zr = results["zonal"]
+        zl = {"z_max": z_max, "t_tol_K": t_tol, "mapped_frac": float(Zr["mapped"].mean())}
+        if "persistent" in results:
+            P = results["persistent"]
+            zl["speedup_vs_persistent"] = Zr["cells_per_s"] / P["cells_per_s"]
+            m = Zr["mapped"]
+            # what mapping changes against integrating every cell
+            zl["max_abs_dT_mapped_K"] = float(np.abs(Zr["T"][m] - P["T"][m]).max()) if m.any() else 0.0
+        line["zonal"] = zl
     if training is not None:
         line["training"] = training
     if tuned is not None:

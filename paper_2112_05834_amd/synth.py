@@ -434,7 +434,7 @@ WORKLOADS = {
     "spray54_heavytail_1048576": Workload("spray54_heavytail_1048576", "spray54", 1048576, 6.0e6,
                                           1e-6, 103, "heavytail", n_steps=10),
     "large160_524288": Workload("large160_524288", "large160", 524288, 4.0e6, 5e-7, 105, "bimodal"),
-    "spray54_ambient_262144": Workload("spray54_ambient_262144", "spray54", 262144, 6.0e6, 1e-6, 106,
+    "spray54_ambient_262144": Workload("spray54_ambient_262144", "spray54", 262144, 6.0e6, 1e-6, 102,
                                        "ambient"),
 }
 
@@ -508,10 +508,12 @@ def generate_states(mech: Mechanism, n_cells: int, pressure: float, recipe: str,
                   0.23:0.77 oxidiser:inert), 30% hot products-rich cells
                   (T ~ N(2200, 150^2) K, 256 templates with 1% log-normal
                   composition noise and +-5 K)
-      ambient   - the bimodal recipe, then 60% of the cells replaced by
-                  ambient oxidiser-side gas (Spray A's hot ambient before
-                  the spray reaches it): oxidiser:inert 0.23:0.77 with the
-                  1e-12 floor of the unburnt cells, T = 900 K + U[-0.5, 0.5] K
+      ambient   - the bimodal recipe with the same seed, then 60% of the
+                  cells (drawn from a second stream, independent of the
+                  first) replaced by ambient oxidiser-side gas (Spray A's
+                  hot ambient before the spray reaches it): oxidiser:inert
+                  0.23:0.77 with the 1e-12 floor of the unburnt cells,
+                  T = 900 K + U[-0.5, 0.5] K
       heavytail - T log-spaced over [700, 2600] K, composition blended
                   between unburnt and hot templates by (T-700)/1900; 5% of
                   the cells are ignition-front cells with T ~ U[1100, 1600] K
@@ -537,6 +539,7 @@ def generate_states(mech: Mechanism, n_cells: int, pressure: float, recipe: str,
         phi[:, 2:] = Y
     elif recipe == "ambient":
         phi = generate_states(mech, n_cells, pressure, "bimodal", seed)
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 1])))
         amb = rng.uniform(size=n_cells) < 0.6
         na = int(amb.sum())
         Y = np.full(ns, 1e-12)
