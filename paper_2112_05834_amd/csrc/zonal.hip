@@ -9,8 +9,9 @@
 //   takes the reference's change of T and Y over the step. Every other cell
 //   is integrated.
 //
-// All of this is streaming work next to the integration, so the kernels are
-// plain one-thread-per-cell (or per element) passes. Z is summed in natural
+// All of this is streaming work next to the integration: one thread per cell
+// or per element, except the classification, which stages rows through LDS so
+// that its loads coalesce. Z is summed in natural
 // species order with one fused multiply-add per term, so that a cell's zone
 // decision does not depend on how the work is split.
 #include "zonal.hpp"
@@ -57,17 +58,76 @@ __global__ void k_zone_reset(unsigned long long* ctl) {
   }
 }
 
-// One atomic per wave: its lowest zone lane holds its lowest zone cell.
-__global__ void k_zone_classify(ZoneArgs a) {
-  const long long c = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x;
-  bool zone = false;
-  if (c < a.n) {
-    zone = z_of(a.phi_in + c * (a.ns + 2) + 2, a.coef, a.ns, a.streams) <= a.z_max;
-    a.flag[c] = zone ? 1 : 0;
-  }
+// Zone flag of one cell, and one atomic per wave for the reference: the
+// lowest zone lane holds the wave's lowest zone cell.
+__device__ __forceinline__ void classify_one(const ZoneArgs& a, long long c, double z) {
+  const bool zone = c < a.n && z <= a.z_max;
+  if (c < a.n) a.flag[c] = zone ? 1 : 0;
   const unsigned long long m = __ballot(zone);
   if (m && static_cast<unsigned long long>(__lane_id()) == static_cast<unsigned long long>(__builtin_ctzll(m)))
     atomicMin(a.ctl, static_cast<unsigned long long>(c));
+}
+
+// Each thread walks its own row (used above kStageMaxNs species).
+__global__ void k_zone_classify(ZoneArgs a) {
+  const long long c = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x;
+  const double z = c < a.n ? z_of(a.phi_in + c * (a.ns + 2) + 2, a.coef, a.ns, a.streams) : 0.0;
+  classify_one(a, c, z);
+}
+
+// One block per 64 consecutive cells: their rows, contiguous in HBM, are
+// loaded 16 bytes per thread by all four waves, coalesced, into LDS (mass
+// fractions only; the row stride is padded to an odd number of doubles so
+// that a lane-per-row read spreads over the banks). Wave 0 then sums each
+// row in species order, the same chain as the row walk.
+constexpr int kStageMaxNs = 127;    // 64 rows of at most 127 doubles: < 64 KB
+constexpr int kStageThreads = 256;
+__global__ void __launch_bounds__(kStageThreads) k_zone_classify_staged(ZoneArgs a) {
+  extern __shared__ double Ys[];    // [64][ns | 1]
+  const int ns = a.ns, stride = ns + 2, ls = ns | 1;
+  const long long c0 = static_cast<long long>(blockIdx.x) * 64;
+  const long long rows = min(64LL, a.n - c0);
+  const int t = threadIdx.x;
+  // rows hold an even number of doubles and phi is 16-byte aligned, so the
+  // block's span is a whole number of 16-byte pairs, none split across rows
+  const double2* src = reinterpret_cast<const double2*>(a.phi_in + c0 * stride);
+  const int pairs = static_cast<int>(rows) * stride / 2;
+  // Row of element e: e < 64 * 129 and the distance from (e + 0.5) / stride
+  // to the nearest integer is at least 0.5 / stride, far above the float
+  // error of the product, so truncation gives floor(e / stride).
+  const float inv = 1.0f / static_cast<float>(stride);
+  constexpr int kBatch = 8;   // loads in flight per thread before their stores
+  for (int q0 = t; q0 < pairs; q0 += kBatch * kStageThreads) {
+    double2 v[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int q = q0 + j * kStageThreads;
+      if (q < pairs) v[j] = src[q];
+    }
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int q = q0 + j * kStageThreads;
+      if (q < pairs) {
+        const int e = 2 * q;
+        const int r = static_cast<int>((static_cast<float>(e) + 0.5f) * inv);
+        const int k = e - r * stride;   // even: k and k + 1 are in row r
+        if (k >= 2) {
+          Ys[r * ls + k - 2] = v[j].x;
+          Ys[r * ls + k - 1] = v[j].y;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (t >= 64) return;
+  double z = 0.0;
+  if (t < rows) {
+    const double bf = a.streams[0], bo = a.streams[1];
+    double b = 0.0;
+    for (int i = 0; i < ns; ++i) b = fma(Ys[t * ls + i], a.coef[i], b);
+    z = (b - bo) / (bf - bo);
+  }
+  classify_one(a, c0 + t, z);
 }
 
 // Mapped flags and the queue order of the integrated cells: each wave claims
@@ -150,7 +210,14 @@ hipError_t launch_zone_classify(const ZoneArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_zone_reset, dim3(1), dim3(64), 0, st, a.ctl);
   if (hipError_t e = hipGetLastError()) return e;
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zone_classify, dim3(grid_for(a.n)), dim3(kThreads), 0, st, a);
+  const bool aligned = (reinterpret_cast<uintptr_t>(a.phi_in) & 15) == 0;
+  if (a.ns <= kStageMaxNs && a.ns % 2 == 0 && aligned) {
+    const size_t lds = sizeof(double) * 64 * (a.ns | 1);
+    hipLaunchKernelGGL(k_zone_classify_staged, dim3(static_cast<unsigned>((a.n + 63) / 64)), dim3(kStageThreads),
+                       lds, st, a);
+  } else {
+    hipLaunchKernelGGL(k_zone_classify, dim3(grid_for(a.n)), dim3(kThreads), 0, st, a);
+  }
   return hipGetLastError();
 }
 
