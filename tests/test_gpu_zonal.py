@@ -115,6 +115,28 @@ def test_zonal_against_oracle(tmp_path, mech_name, n):
     _check_mapped(phi, out, mapped, ref, na, nr, st)
 
 
+def test_zone_boundary_is_decided_in_the_same_bits(tmp_path):
+    """z_max set to one cell's Z exactly (as the oracle computes it) puts that
+    cell in the zone; the next double below takes it out. Only a Z with the
+    oracle's bits gets both right."""
+    mech, path, phi = _states("spray54", 1000, str(tmp_path))
+    c, yf, yo = synth.bilger_streams(mech)
+    z = O.Mech(path).mixture_fraction(c, yf, yo, phi)
+    # k: a fuel-bearing cell of median Z, unique to it; the reference stays the
+    # first ambient cell, and t_tol = 1e4 K maps every other zone cell
+    rest = np.nonzero(z > Z_MAX)[0]
+    k = int(rest[np.argsort(z[rest])[len(rest) // 2]])
+    assert (z == z[k]).sum() == 1 and k > np.nonzero(z <= Z_MAX)[0][0]
+    x = _to(phi)
+    for zm, inside in ((z[k], True), (np.nextafter(z[k], -np.inf), False)):
+        S = _solver(path, mech, z_max=float(zm), t_tol=1e4)
+        _, m = S.integrate_zonal(x, 1e-6)
+        mapped = m.cpu().numpy().astype(bool)
+        want, _ = _rule(z, phi[:, 0], zm, 1e4)
+        assert np.array_equal(mapped, want)
+        assert mapped[k] == inside
+
+
 def test_zonal_full_size_workload(tmp_path):
     """The ambient spray workload at full size (262 144 cells) in the launch
     configuration of the benchmark."""
