@@ -226,6 +226,37 @@ def test_zonal_degenerate_cases(tmp_path):
     assert np.array_equal(out[1:], phi[1:])
 
 
+def test_zonal_null_mapped_and_cells_per_wave(tmp_path):
+    """Through the C ABI with mapped = NULL (the solver's own flag buffer),
+    and with 1 and 4 cells per wave of the 10-component kernel: the same
+    bits every time."""
+    import ctypes
+    mech, path, phi = _states("tiny9", 777, str(tmp_path))
+    x = _to(phi)
+    outs = []
+    for cpw in (1, 4):
+        S = _solver(path, mech, cells_per_wave=cpw)
+        r, m = S.integrate_zonal(x, 1e-6)
+        outs.append((_np(r), m.cpu().numpy()))
+        o = torch.empty_like(x)
+        na = torch.empty(777, dtype=torch.int32, device=DEV)
+        nr = torch.empty_like(na)
+        st = torch.empty(777, dtype=torch.int8, device=DEV)
+        h = torch.zeros(777, dtype=torch.float64, device=DEV)
+        vp = ctypes.c_void_p
+        rc = chem.lib().chem_integrate_zonal(S._h, 777, 1e-6, vp(x.data_ptr()), vp(o.data_ptr()), vp(h.data_ptr()),
+                                             vp(na.data_ptr()), vp(nr.data_ptr()), vp(st.data_ptr()), None,
+                                             vp(torch.cuda.current_stream().cuda_stream))
+        assert rc == 0
+        torch.cuda.synchronize()
+        for u, v in zip(_np(r), (o.cpu().numpy(), h.cpu().numpy(), na.cpu().numpy(), nr.cpu().numpy(),
+                                 st.cpu().numpy())):
+            assert np.array_equal(u, v)
+    for u, v in zip(outs[0][0], outs[1][0]):
+        assert np.array_equal(u, v)
+    assert np.array_equal(outs[0][1], outs[1][1]) and outs[0][1].sum() > 300
+
+
 def test_zone_config_errors(tmp_path):
     mech, path, _ = _states("tiny9", 4, str(tmp_path))
     S = chem.Solver(chem.Mechanism(path), chem.default_opts())
