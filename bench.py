@@ -89,10 +89,14 @@ def measured_fp64_ops(kernel_src):
     return float(t.group(1)) if h.startswith(m.group(1)) else None
 
 
+# integration tolerances of every solver the benchmark configures
+TOL = {"rtol": 1e-6, "atol": 1e-10}
+
+
 def time_schedule(S, chem, torch, x, dt, steps, warmup, chain, zonal=False, **opts):
     """(last result, wall s, per-step event ms, per-launch kernel ms). zonal:
     one step with zonal reference mapping (chem_integrate_zonal) per step."""
-    S.set_opts(chem.default_opts(**opts))
+    S.set_opts(chem.default_opts(**TOL, **opts))
     out = torch.empty_like(x)
 
     def one():
@@ -127,7 +131,7 @@ def train_model(S, chem, torch, synth, wl, mech, seeds, log, n_cells):
     one persistent step each, then train the predictor on all of them."""
     t0 = time.perf_counter()
     feats, targ = [], []
-    S.set_opts(chem.default_opts(schedule=chem.PERSISTENT))
+    S.set_opts(chem.default_opts(schedule=chem.PERSISTENT, **TOL))
     for sd in seeds:
         phi = synth.generate_states(mech, wl.n_cells, wl.pressure, wl.recipe, sd)[:n_cells]
         x = torch.from_numpy(phi.copy()).to("cuda:0")
@@ -163,7 +167,7 @@ def cpu_baseline(path, phi, dt, budget_s, seed):
     t0 = time.perf_counter()
     while done < len(idx) and time.perf_counter() - t0 < budget_s:
         sel = idx[done:done + chunk]
-        M.integrate(phi[sel], dt, n_threads=cores)
+        M.integrate(phi[sel], dt, n_threads=cores, **TOL)
         done += len(sel)
     wall = time.perf_counter() - t0
     return {"value": done / wall, "unit": "cells/s", "cores": cores, "kind": "oracle",
@@ -184,6 +188,8 @@ def main():
                     help="log the cost model's training samples on the first N cells of each training seed "
                          "(default: as many cells as the workload)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--rtol", type=float, default=1e-6, help="relative tolerance (default: the Spray A setting)")
+    ap.add_argument("--atol", type=float, default=1e-10, help="absolute tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedules", default="plain,persistent,binned,truebins",
                     help="comma list of plain, persistent, binned, truebins, zonal")
@@ -194,6 +200,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
+    TOL.update(rtol=args.rtol, atol=args.atol)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
               "(cells are independent: a multi-GPU run would give each GPU its own share of the cells)" % args.gpus,
@@ -211,7 +218,7 @@ def main():
     d = tempfile.mkdtemp(prefix="chem_bench_")
     wl, mech, path, phi = synth.workload_inputs(args.workload, d, args.cells if args.cells > 0 else None)
     M = chem.Mechanism(path)
-    S = chem.Solver(M, chem.default_opts(), device=0)
+    S = chem.Solver(M, chem.default_opts(**TOL), device=0)
     x = torch.from_numpy(phi).to("cuda:0")
     if args.copy_calibration > 0:
         nb = args.copy_calibration << 20
@@ -242,7 +249,7 @@ def main():
         sample = torch.from_numpy(np.ascontiguousarray(phi[idx])).to("cuda:0")
         tuned = {}
         for sched in ("persistent",):
-            S.set_opts(chem.default_opts(schedule=chem.PERSISTENT))
+            S.set_opts(chem.default_opts(schedule=chem.PERSISTENT, **TOL))
             S.autotune(sample, wl.dt)
             o = S.opts
             tuned = {"waves_per_block": o.waves_per_block, "queue_chunk": o.queue_chunk,
@@ -305,7 +312,8 @@ def main():
     src = os.path.join(ROOT, "paper_2112_05834_amd", "csrc", "integrator.hip")
     traffic = measured_traffic(src)
     executed = measured_fp64_ops(src)
-    if args.workload != "spray54_262144" or args.chain > 1 or args.cells > 0:
+    if (args.workload != "spray54_262144" or args.chain > 1 or args.cells > 0 or
+            (args.rtol, args.atol) != (1e-6, 1e-10)):
         traffic = None
         executed = None
     steps_total = args.steps * args.chain
@@ -324,7 +332,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "cells": n_cells, "species": mech.n_species,
                    "reactions": mech.n_reactions, "pressure_Pa": wl.pressure, "dt_s": wl.dt,
-                   "schedule": head, "chained_steps_per_graph": args.chain, "rtol": 1e-6, "atol": 1e-10},
+                   "schedule": head, "chained_steps_per_graph": args.chain, "rtol": args.rtol, "atol": args.atol},
         "roofline": {"bound": "alu", "achieved": None if achieved is None else achieved / 1e12,
                      "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": None if achieved is None else achieved / FP64_VECTOR_PEAK,

@@ -158,6 +158,23 @@ def heavy(tmp_path_factory):
     return synth.workload_inputs("spray54_heavytail_1048576", d)
 
 
+def test_spray_shear_layer_tolerances_sampled(spray):
+    """The looser tolerance pair of the paper's 2-D shear-layer runs (atol
+    1e-8, rtol 1e-5) on sampled cells of the full spray workload."""
+    wl, mech, path, phi = spray
+    S = chem.Solver(chem.Mechanism(path), chem.default_opts(schedule=chem.PERSISTENT, rtol=1e-5, atol=1e-8))
+    r = S.integrate(_to(phi), wl.dt)
+    torch.cuda.synchronize()
+    idx = synth.sample_indices(phi.shape[0], 96, 23)
+    ref = O.Mech(path).integrate(phi[idx], wl.dt, rtol=1e-5, atol=1e-8, n_threads=NCPU)
+    na, nr = r.n_acc.cpu().numpy()[idx], r.n_rej.cpu().numpy()[idx]
+    assert np.array_equal(r.status.cpu().numpy()[idx], ref[4])
+    _compare(phi[idx], r.phi.cpu().numpy()[idx], ref[0], (na, nr), (ref[2], ref[3]), frac_diff=0.02)
+    # fewer substeps than at the default tolerances on the same cells
+    base = O.Mech(path).integrate(phi[idx], wl.dt, n_threads=NCPU)
+    assert (ref[2] + ref[3]).sum() < (base[2] + base[3]).sum()
+
+
 def test_heavytail_chained_full_size_sampled(heavy):
     """1 048 576 heavy-tailed cells, ten chained steps captured in one HIP
     graph on the persistent queue with 4 waves per block and chunk 1: 40
