@@ -161,7 +161,7 @@ def cpu_baseline(path, phi, dt, budget_s, seed):
 
     from oracle import oracle as O
     idx = np.random.Generator(np.random.PCG64(seed)).permutation(phi.shape[0])[:65536]
-    cores = os.cpu_count() or 1
+    cores = min(16, os.cpu_count() or 1)     # a one-GPU share of the host
     M = O.Mech(path)
     done, chunk = 0, 4 * cores
     t0 = time.perf_counter()
@@ -170,9 +170,19 @@ def cpu_baseline(path, phi, dt, budget_s, seed):
         M.integrate(phi[sel], dt, n_threads=cores, **TOL)
         done += len(sel)
     wall = time.perf_counter() - t0
+    # the same oracle on one thread, on the next cells of the sample, for a
+    # quarter of the budget
+    one, t1 = 0, time.perf_counter()
+    while done + one < len(idx) and time.perf_counter() - t1 < budget_s / 4:
+        sel = idx[done + one:done + one + 8]
+        M.integrate(phi[sel], dt, n_threads=1, **TOL)
+        one += len(sel)
+    wall1 = time.perf_counter() - t1
     return {"value": done / wall, "unit": "cells/s", "cores": cores, "kind": "oracle",
             "sample": "%d cells drawn uniformly at random (seed %d) from the workload, in chunks of %d until "
-                      "%.0f s had passed; %d host threads, %.1f s wall" % (done, seed, chunk, budget_s, cores, wall)}
+                      "%.0f s had passed; %d host threads, %.1f s wall" % (done, seed, chunk, budget_s, cores, wall),
+            "value_1_thread": one / wall1 if one else None,
+            "sample_1_thread": "the next %d cells of the same sample on one thread, %.1f s wall" % (one, wall1)}
 
 
 def main():
