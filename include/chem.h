@@ -295,8 +295,11 @@ int chem_mixture_fraction(chem_solver* s, int64_t n_cells, const double* phi, do
  * unchanged, n_acc = n_rej = 0, the reference's status, and its h_io left as
  * it was. mapped: device int8 [n] out (1 mapped, 0 integrated), or NULL.
  * The integrated cells always go through the persistent queue (learned
- * binning is not applied to them). Enqueue only, no host synchronisation.
- * The solver's zone buffers are shared by its calls: do not overlap two
+ * binning is not applied to them). Enqueue only, no host synchronisation,
+ * except that a call with more cells than any earlier one first synchronises
+ * the stream and allocates the solver's flag and order buffers (int8 and
+ * int32 per cell), so capture such a call only after one of at least its
+ * size. The solver's zone buffers are shared by its calls: do not overlap two
  * zonal calls of one solver on different streams. n_cells at most
  * 2^31 - 1. Errors: as chem_integrate, plus CHEM_ESTATE (no
  * chem_zone_config yet). */
