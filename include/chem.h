@@ -280,8 +280,9 @@ int chem_mech_elements(const chem_mech* m, int32_t* n_elements, int32_t* counts)
  * z_max and t_tol [K] are compared with <=. Allocates the solver's zone
  * buffers on first use and synchronises the device. Errors: CHEM_EINVAL (NULL
  * or non-finite argument, t_tol < 0, or streams with the same beta),
- * CHEM_EHIP. Do not call while a zonal integration of this solver is in
- * flight. */
+ * CHEM_EHIP; after an error the solver has no zone definition until the
+ * next successful call. Do not call while a zonal integration of this solver
+ * is in flight. */
 int chem_zone_config(chem_solver* s, const double* coupling, const double* y_fuel, const double* y_ox,
                      double z_max, double t_tol);
 

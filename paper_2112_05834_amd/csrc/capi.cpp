@@ -1038,6 +1038,7 @@ int chem_zone_config(chem_solver* s, const double* coupling, const double* y_fue
       return fail(CHEM_EINVAL, "chem_zone_config: non-finite stream composition");
   DeviceGuard g(s->dev);
   HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  s->zone_ready = false;       // until the new definition is in place
   const int ns = s->ns, ne = s->ne;
   if (!s->d_zone) {
     HIP_TRY(hipMalloc(&s->d_zone, sizeof(double) * (2 * ns + 4)), "hipMalloc zone");
@@ -1064,7 +1065,6 @@ int chem_zone_config(chem_solver* s, const double* coupling, const double* y_fue
   hipFree(d_in);
   if (e != hipSuccess) return hip_fail(e, "zone setup");
   if (!(streams[0] != streams[1]) || !std::isfinite(streams[0]) || !std::isfinite(streams[1])) {
-    s->zone_ready = false;
     return fail(CHEM_EINVAL, "chem_zone_config: fuel and oxidiser streams have the same coupling value");
   }
   s->z_max = z_max;

@@ -265,8 +265,13 @@ def test_zone_config_errors(tmp_path):
         S.integrate_zonal(x, 1e-6)
     assert e.value.code == -5
     c, yf, yo = synth.bilger_streams(mech)
+    S.zone_config(c, yf, yo, Z_MAX, T_TOL)
     with pytest.raises(chem.ChemError):
         S.zone_config(c, yo, yo, Z_MAX, T_TOL)
+    # a failed configuration leaves no zone definition behind
+    with pytest.raises(chem.ChemError) as e:
+        S.integrate_zonal(x, 1e-6)
+    assert e.value.code == -5
     with pytest.raises(chem.ChemError):
         S.zone_config(c, yf, yo, Z_MAX, -1.0)
     with pytest.raises(chem.ChemError):
