@@ -25,6 +25,15 @@ def _to(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
 
 
+def _compare_h(h_gpu, h_ref, same, what):
+    """The proposed next substep (h_io out) on cells with the oracle's step
+    sequence: the controller's factor goes as err^(-1/3), so last-bit
+    differences of the error estimate move it far below 1e-6."""
+    rel = np.abs(h_gpu - h_ref) / np.abs(h_ref)
+    print("%s: max relative difference of h_io out %.2e" % (what, rel[same].max() if same.any() else 0.0))
+    assert (h_ref > 0).all() and (rel[same] <= 1e-6).all()
+
+
 def _compare(phi0, gpu, ref, counts_gpu, counts_ref, frac_diff=1e-3):
     na, nr = counts_gpu
     ona, onr = counts_ref
@@ -132,6 +141,8 @@ def test_integrate_tiny_all_cells(tiny):
     assert np.array_equal(r.status.cpu().numpy(), st)
     same = _compare(phi, r.phi.cpu().numpy(), ref, (r.n_acc.cpu().numpy(), r.n_rej.cpu().numpy()), (na, nr))
     print("tiny: %d/1024 cells with identical step sequence" % same)
+    eq = (r.n_acc.cpu().numpy() == na) & (r.n_rej.cpu().numpy() == nr)
+    _compare_h(r.h.cpu().numpy(), h, eq, "tiny")
 
 
 def test_integrate_spray_full_size_sampled(spray):
@@ -148,6 +159,8 @@ def test_integrate_spray_full_size_sampled(spray):
     assert (gst == 0).all()
     _compare(phi[idx], r.phi.cpu().numpy()[idx], ref,
              (r.n_acc.cpu().numpy()[idx], r.n_rej.cpu().numpy()[idx]), (na, nr), frac_diff=0.02)
+    eq = (r.n_acc.cpu().numpy()[idx] == na) & (r.n_rej.cpu().numpy()[idx] == nr)
+    _compare_h(r.h.cpu().numpy()[idx], h, eq, "spray")
     out = r.phi.cpu().numpy()
     assert np.abs(out[:, 2:].sum(axis=1) - 1.0).max() < 1e-12
 
@@ -202,6 +215,7 @@ def test_heavytail_chained_full_size_sampled(heavy):
         nr += b
     out = r.phi.cpu().numpy()
     same = _compare(phi[idx], out[idx], cur, (gna[idx], gnr[idx]), (na, nr), frac_diff=0.05)
+    _compare_h(h.cpu().numpy()[idx], hh, (gna[idx] == na) & (gnr[idx] == nr), "heavytail")
     print("heavytail: %d/%d sampled cells with identical counts; substeps of the costliest %s"
           % (same, len(idx), (gna + gnr)[top].tolist()))
     assert np.abs(out[:, 2:].sum(axis=1) - 1.0).max() < 1e-11
