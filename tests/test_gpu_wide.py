@@ -131,6 +131,11 @@ def test_wide_integrate_matches_oracle(large):
     assert np.array_equal(r.status.cpu().numpy(), st)
     same = _compare(x, r.phi.cpu().numpy(), ref, (r.n_acc.cpu().numpy(), r.n_rej.cpu().numpy()), (na, nr))
     print("large160: %d/%d cells with identical step sequence, substeps %s" % (same, len(idx), (na + nr).tolist()))
+    # the proposed next substep (h_io out) on cells with the oracle's step sequence
+    eq = (r.n_acc.cpu().numpy() == na) & (r.n_rej.cpu().numpy() == nr)
+    rel = np.abs(r.h.cpu().numpy() - h) / h
+    print("large160: max relative difference of h_io out %.2e" % rel[eq].max())
+    assert (h > 0).all() and (rel[eq] <= 1e-6).all()
 
 
 def _run(S, x, dt, **opts):
