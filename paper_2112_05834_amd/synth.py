@@ -436,6 +436,8 @@ WORKLOADS = {
     "large160_524288": Workload("large160_524288", "large160", 524288, 4.0e6, 5e-7, 105, "bimodal"),
     "spray54_ambient_262144": Workload("spray54_ambient_262144", "spray54", 262144, 6.0e6, 1e-6, 102,
                                        "ambient"),
+    "large160_ambient_524288": Workload("large160_ambient_524288", "large160", 524288, 4.0e6, 5e-7, 105,
+                                        "ambient"),
 }
 
 # Weights of the elements in Bilger's coupling function, per mole of atoms:
