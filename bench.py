@@ -73,6 +73,25 @@ def measured_traffic(kernel_src):
     return float(t.group(1)) * 1e6 if h.startswith(m.group(1)) else None
 
 
+def measured_wide_traffic():
+    """HBM bytes per launch of the workgroup kernel on the first 16384 cells of
+    the 160-species workload (persistent schedule), from the committed counter
+    summary, if it was taken on the current sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "k_integrate_wide_large160_16384_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    t = re.search(r"total ([0-9.]+) TB\.", text)
+    if not t:
+        return None
+    for src in ("integrator_wide.hip", "device_common.hpp"):
+        m = re.search(re.escape(src) + r" sha256 prefix ([0-9a-f]+)", text)
+        full = os.path.join(ROOT, "paper_2112_05834_amd", "csrc", src)
+        if not m or not hashlib.sha256(open(full, "rb").read()).hexdigest().startswith(m.group(1)):
+            return None
+    return float(t.group(1)) * 1e12
+
+
 def measured_fp64_ops(kernel_src):
     """Executed FP64 operations per launch (all lanes) from the committed FP64
     instruction-counter summary, if it was taken on the current kernel source
@@ -369,7 +388,11 @@ def main():
         fp64 = line["roofline"]
         line["roofline"] = {"bound": "hbm", "achieved": None if kern_s is None else hb / kern_s / 1e9,
                             "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                            "frac": None if kern_s is None else hb / kern_s / HBM_PEAK, "traffic": None,
+                            "frac": None if kern_s is None else hb / kern_s / HBM_PEAK,
+                            # measured bytes exist for one configuration: these cells, this schedule
+                            "traffic": measured_wide_traffic() if (
+                                args.workload == "large160_524288" and n_cells == 16384 and args.chain == 1 and
+                                head == "persistent" and (args.rtol, args.atol) == (1e-6, 1e-10)) else None,
                             "kernel": "k_integrate_wide (%s schedule)" % head, "bytes_per_launch": hb,
                             "kernel_ms": fp64["kernel_ms"],
                             "fp64": {"achieved": fp64["achieved"], "peak": fp64["peak"], "unit": "TFLOP/s",
