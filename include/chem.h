@@ -132,7 +132,10 @@ int chem_integrate(chem_solver* s, int64_t n_cells, double dt, const double* phi
  * holds the final state, n_acc / n_rej accumulate over the steps and status is
  * the first non-zero status of the steps. phi_in is not modified; the library
  * ping-pongs through an internal buffer. The graph is cached per (pointers,
- * sizes, options) and rebuilt when they change. Errors as chem_integrate. */
+ * sizes, options) and rebuilt when they change. If the caller is capturing the
+ * stream already, the steps go straight into the caller's graph and the
+ * solver's own graph is left alone; call once outside the capture first, so
+ * that the internal buffers exist. Errors as chem_integrate. */
 int chem_integrate_steps(chem_solver* s, int32_t n_steps, int64_t n_cells, double dt,
                          const double* phi_in, double* phi_out, double* h_io, int32_t* n_acc,
                          int32_t* n_rej, int8_t* status, void* stream);

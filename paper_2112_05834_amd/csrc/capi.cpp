@@ -523,6 +523,25 @@ int chem_integrate(chem_solver* s, int64_t n, double dt, const double* in, doubl
   return launch_step(s, s->opts, n, dt, in, out, h_io, n_acc, n_rej, status, 0, perm, st);
 }
 
+}  // extern "C"
+
+// The steps enqueued one after the other on st (no graph of the solver's own):
+// used when the caller is capturing st already.
+static int enqueue_steps(chem_solver* s, int32_t n_steps, int64_t n, double dt, const double* in, double* out,
+                         double* h_io, int32_t* n_acc, int32_t* n_rej, int8_t* status, hipStream_t st) {
+  for (int32_t step = 0; step < n_steps; ++step) {
+    const double* src = step == 0 ? in : ((n_steps - step) % 2 == 0 ? out : s->d_ping);
+    double* dst = ((n_steps - 1 - step) % 2 == 0) ? out : s->d_ping;
+    const int* perm = nullptr;
+    if (s->opts.schedule == CHEM_PERSISTENT_BINNED)
+      if (int rc = binned_perm(s, n, dt, src, st, &perm)) return rc;
+    if (int rc = launch_step(s, s->opts, n, dt, src, dst, h_io, n_acc, n_rej, status, step > 0, perm, st)) return rc;
+  }
+  return CHEM_OK;
+}
+
+extern "C" {
+
 int chem_integrate_steps(chem_solver* s, int32_t n_steps, int64_t n, double dt, const double* in, double* out,
                          double* h_io, int32_t* n_acc, int32_t* n_rej, int8_t* status, void* stream) {
   if (int rc = check_integrate_args(s, n, dt, in, out)) return rc;
@@ -542,19 +561,17 @@ int chem_integrate_steps(chem_solver* s, int32_t n_steps, int64_t n, double dt, 
     HIP_TRY(hipMalloc(&s->d_ping, static_cast<size_t>(n) * w * sizeof(double)), "hipMalloc ping buffer");
     s->ping_cells = static_cast<size_t>(n);
   }
+  // the caller is capturing already: enqueue the steps into its graph, and
+  // leave the solver's own graph alone (no graph calls during the capture)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(st, &cs), "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone) return enqueue_steps(s, n_steps, n, dt, in, out, h_io, n_acc, n_rej, status, st);
   auto& k = s->gkey;
   const bool same = s->graph && k.n_steps == n_steps && k.n_cells == n && k.dt == dt && k.in == in && k.out == out &&
                     k.h == h_io && k.a == n_acc && k.r == n_rej && k.s == status && k.st == st &&
                     std::memcmp(&k.o, &s->opts, sizeof(chem_opts)) == 0;
   if (!same) {
     drop_graph(s);
-    hipStreamCaptureStatus cs;
-    HIP_TRY(hipStreamIsCapturing(st, &cs), "hipStreamIsCapturing");
-    const bool outer_capture = cs != hipStreamCaptureStatusNone;
-    if (outer_capture) {
-      // the caller is capturing already: enqueue the steps into its graph
-      goto enqueue_direct;
-    }
     // capture on the solver's own stream (the caller's may be the null
     // stream, which cannot be captured); the graph is launched on st
     hipStream_t cst = s->capture_stream;
@@ -599,17 +616,6 @@ int chem_integrate_steps(chem_solver* s, int32_t n_steps, int64_t n, double dt, 
     }
   }
   HIP_TRY(hipGraphLaunch(s->graph, st), "hipGraphLaunch");
-  return CHEM_OK;
-
-enqueue_direct:
-  for (int32_t step = 0; step < n_steps; ++step) {
-    const double* src = step == 0 ? in : ((n_steps - step) % 2 == 0 ? out : s->d_ping);
-    double* dst = ((n_steps - 1 - step) % 2 == 0) ? out : s->d_ping;
-    const int* perm = nullptr;
-    if (s->opts.schedule == CHEM_PERSISTENT_BINNED)
-      if (int rc = binned_perm(s, n, dt, src, st, &perm)) return rc;
-    if (int rc = launch_step(s, s->opts, n, dt, src, dst, h_io, n_acc, n_rej, status, step > 0, perm, st)) return rc;
-  }
   return CHEM_OK;
 }
 

@@ -257,6 +257,37 @@ def test_zonal_null_mapped_and_cells_per_wave(tmp_path):
     assert np.array_equal(outs[0][1], outs[1][1]) and outs[0][1].sum() > 300
 
 
+def test_zonal_and_chained_steps_captured_by_the_caller(tmp_path):
+    """A caller's own graph capture (torch.cuda.graph) of a zonal call and of
+    chained steps, after one eager call of each has allocated the solver's
+    buffers: every replay, with eager work and synchronisation between the
+    replays, gives the eager call's bits."""
+    mech, path, phi = _states("spray54", 2048, str(tmp_path))
+    S = _solver(path, mech)
+    x = _to(phi)
+    out_z = torch.empty_like(x)
+    out_c = torch.empty_like(x)
+    rz, mz = S.integrate_zonal(x, 1e-6, h_io=False, out=out_z)
+    rc = S.integrate_steps(x, 1e-6, 3, h_io=False, out=out_c)
+    torch.cuda.synchronize()
+    want = [t.clone() for t in (rz.phi, rz.n_acc, rz.n_rej, rz.status, mz, rc.phi, rc.n_acc, rc.n_rej, rc.status)]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gz, gm = S.integrate_zonal(x, 1e-6, h_io=False, out=out_z)
+        gc = S.integrate_steps(x, 1e-6, 3, h_io=False, out=out_c)
+    for rep in range(3):
+        out_z.fill_(-1.0)
+        out_c.fill_(-1.0)
+        junk = (x * 2.0).sum()                     # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = (gz.phi, gz.n_acc, gz.n_rej, gz.status, gm, gc.phi, gc.n_acc, gc.n_rej, gc.status)
+        for a, b in zip(got, want):
+            assert torch.equal(a, b), "replay %d differs" % rep
+        assert torch.isfinite(junk)
+
+
 def test_zone_config_errors(tmp_path):
     mech, path, _ = _states("tiny9", 4, str(tmp_path))
     S = chem.Solver(chem.Mechanism(path), chem.default_opts())
