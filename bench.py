@@ -222,8 +222,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedules", default="plain,persistent,binned,truebins",
                     help="comma list of plain, persistent, binned, truebins, zonal")
-    ap.add_argument("--zone", default="1e-6,1.0", metavar="Z_MAX,T_TOL",
-                    help="zonal schedule: cells with Z <= Z_MAX within T_TOL kelvin of the reference are mapped")
+    ap.add_argument("--zone", default="1e-6,1.0", metavar="Z_MAX,T_TOL[,DZ]",
+                    help="zonal schedule: cells with Z <= Z_MAX within T_TOL kelvin of their Z band's reference "
+                         "are mapped (bands of width DZ; default one band)")
     ap.add_argument("--autotune", type=int, default=0, metavar="CELLS",
                     help="pick launch shape and queue chunk by timing a seeded sample of this many cells first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -290,8 +291,10 @@ def main():
     if "zonal" in scheds:
         if args.chain > 1:
             raise SystemExit("the zonal schedule runs one chemistry step per call (--chain 1)")
-        z_max, t_tol = (float(v) for v in args.zone.split(","))
-        S.zone_config(*synth.bilger_streams(mech), z_max, t_tol)
+        zv = [float(v) for v in args.zone.split(",")]
+        z_max, t_tol = zv[0], zv[1]
+        dz = zv[2] if len(zv) > 2 else 0.0
+        S.zone_config(*synth.bilger_streams(mech), z_max, t_tol, dz=dz)
     results = {}
     true_cost = None
     for sched in scheds:
@@ -320,10 +323,10 @@ def main():
         if "zonal" in scheds and sched in ("zonal", "persistent"):
             results[sched]["T"] = r.phi[:, 0].cpu().numpy()
         if sched == "zonal":
-            mapped = S.integrate_zonal(x, wl.dt, h_io=False)[1].cpu().numpy().astype(bool)
+            mapped = S.integrate_zonal(x, wl.dt, h_io=False)[1].cpu().numpy() > 0
             results[sched]["mapped"] = mapped
-            log("zonal: %.1f%% of the cells mapped (Z <= %g, |T - T_ref| <= %g K)" %
-                (100 * mapped.mean(), z_max, t_tol))
+            log("zonal: %.1f%% of the cells mapped (Z <= %g, |T - T_ref| <= %g K, band width %g)" %
+                (100 * mapped.mean(), z_max, t_tol, dz))
         log("%s %.1f ms/step (events %s), kernel ms %s, %.4e cells/s, failed cells %d, binning used %s" %
             (sched, 1e3 * wall / (args.steps * args.chain), ["%.1f" % m for m in ms],
              ["%.1f" % m for m in kms[:4]], cells / wall, int((stt != 0).sum()), used))
@@ -401,7 +404,7 @@ def main():
         line["speedup_vs_plain"] = R["cells_per_s"] / results["plain"]["cells_per_s"]
     if "zonal" in results:
         Zr = results["zonal"]
-        zl = {"z_max": z_max, "t_tol_K": t_tol, "mapped_frac": float(Zr["mapped"].mean())}
+        zl = {"z_max": z_max, "t_tol_K": t_tol, "band_width": dz, "mapped_frac": float(Zr["mapped"].mean())}
         if "persistent" in results:
             P = results["persistent"]
             zl["speedup_vs_persistent"] = Zr["cells_per_s"] / P["cells_per_s"]

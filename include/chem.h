@@ -289,6 +289,13 @@ int chem_mech_elements(const chem_mech* m, int32_t* n_elements, int32_t* counts)
 int chem_zone_config(chem_solver* s, const double* coupling, const double* y_fuel, const double* y_ox,
                      double z_max, double t_tol);
 
+/* Split the zone into bands of Z: band b = floor(max(Z, 0) / dz), each with
+ * its own reference (its cell of lowest index), so that a cell is mapped only
+ * from a reference of similar Z. dz = 0 (the default) keeps the whole zone
+ * as one band. At most 64 bands (floor(z_max / dz) + 1). Errors: CHEM_EINVAL
+ * (dz < 0, non-finite, or too many bands for the configured z_max). */
+int chem_zone_bands(chem_solver* s, double dz);
+
 /* Z of n cells: phi device [n][2+Ns] in, z device [n] FP64 out; enqueued on
  * stream. Errors: CHEM_EINVAL, CHEM_ESTATE (no chem_zone_config yet). */
 int chem_mixture_fraction(chem_solver* s, int64_t n_cells, const double* phi, double* z, void* stream);
@@ -297,7 +304,8 @@ int chem_mixture_fraction(chem_solver* s, int64_t n_cells, const double* phi, do
  * chem_integrate for the integrated cells. A mapped cell gets
  * phi_out = phi_in + (reference's phi_out - phi_in) for T and Y, its p
  * unchanged, n_acc = n_rej = 0, the reference's status, and its h_io left as
- * it was. mapped: device int8 [n] out (1 mapped, 0 integrated), or NULL.
+ * it was. mapped: device int8 [n] out (band + 1 of a mapped cell, so 1 with
+ * one band; 0 for an integrated cell), or NULL.
  * The integrated cells always go through the persistent queue (learned
  * binning is not applied to them). Enqueue only, no host synchronisation,
  * except that a call with more cells than any earlier one first synchronises

@@ -173,31 +173,40 @@ class Mech:
         return z
 
     def integrate_zonal(self, phi, dt: float, coupling, y_fuel, y_ox, z_max: float, t_tol: float,
-                        h_io=None, **kw):
+                        h_io=None, dz: float = 0.0, **kw):
         """Zonal reference mapping around the integrator (paper: Methodology,
         the DLBFoam paragraph: a cell is either solved or mapped from a
         reference solution of similar mixture fraction), read as:
 
-        - the zone is every cell with Z <= z_max; its reference is the zone
-          cell of lowest index;
-        - a zone cell other than the reference whose |T - T_ref| <= t_tol is
-          mapped: it takes the reference's change of state over dt,
+        - the zone is every cell with Z <= z_max. With dz = 0 it is one band;
+          with dz > 0 it is split into bands b = floor(max(Z, 0) / dz), so
+          that a cell is mapped only from a reference of similar Z. Each
+          band's reference is its cell of lowest index;
+        - a zone cell other than its band's reference whose |T - T_ref| <=
+          t_tol is mapped: it takes the reference's change of state over dt,
           T + (T_ref,out - T_ref,in) and Y_k + (Y_ref,out,k - Y_ref,in,k), with
           p, h unchanged, no steps counted and the reference's status;
         - every other cell is integrated as by :meth:`integrate`.
 
-        Returns (phi_out, h, n_acc, n_rej, status, mapped)."""
+        Returns (phi_out, h, n_acc, n_rej, status, mapped), mapped holding
+        the band + 1 of every mapped cell and 0 elsewhere."""
         phi = np.ascontiguousarray(phi, dtype=np.float64)
         n = phi.shape[0]
         z = self.mixture_fraction(coupling, y_fuel, y_ox, phi)
-        zone = np.nonzero(z <= z_max)[0]
-        mapped = np.zeros(n, dtype=bool)
-        ref = -1
-        if zone.size:
-            ref = int(zone[0])
-            for i in zone[1:]:
-                mapped[i] = abs(phi[i, 0] - phi[ref, 0]) <= t_tol
-        solve = np.nonzero(~mapped)[0]
+        band = np.full(n, -1)
+        for i in range(n):
+            if z[i] <= z_max:
+                band[i] = int(np.floor(max(z[i], 0.0) / dz)) if dz > 0 else 0
+        mapped = np.zeros(n, dtype=np.int8)
+        refs = {}
+        for i in range(n):
+            if band[i] < 0:
+                continue
+            if band[i] not in refs:
+                refs[band[i]] = i
+            elif abs(phi[i, 0] - phi[refs[band[i]], 0]) <= t_tol:
+                mapped[i] = band[i] + 1
+        solve = np.nonzero(mapped == 0)[0]
         out = phi.copy()
         h = np.zeros(n) if h_io is None else np.array(h_io, dtype=np.float64)
         na = np.zeros(n, dtype=np.int32)
@@ -207,6 +216,7 @@ class Mech:
             o, hs, a, r, s = self.integrate(phi[solve], dt, h_io=h[solve], **kw)
             out[solve], h[solve], na[solve], nr[solve], st[solve] = o, hs, a, r, s
         for i in np.nonzero(mapped)[0]:
+            ref = refs[mapped[i] - 1]
             out[i, 0] = phi[i, 0] + (out[ref, 0] - phi[ref, 0])
             out[i, 1] = phi[i, 1]
             for k in range(2, phi.shape[1]):

@@ -93,6 +93,7 @@ def lib():
             "chem_kernel_times": (i32, [_vp, _vp, i32, ctypes.POINTER(i32)]),
             "chem_mech_elements": (i32, [_vp, ctypes.POINTER(i32), _vp]),
             "chem_zone_config": (i32, [_vp, _vp, _vp, _vp, dbl, dbl]),
+            "chem_zone_bands": (i32, [_vp, dbl]),
             "chem_mixture_fraction": (i32, [_vp, i64, _vp, _vp, _vp]),
             "chem_integrate_zonal": (i32, [_vp, i64, dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "chem_last_error": (ctypes.c_char_p, []),
@@ -247,17 +248,20 @@ class Solver:
         return Result(phi_out, h, na, nr, st)
 
     # ---- zonal reference mapping ----
-    def zone_config(self, coupling, y_fuel, y_ox, z_max: float, t_tol: float):
+    def zone_config(self, coupling, y_fuel, y_ox, z_max: float, t_tol: float, dz: float = 0.0):
         """Mixture-fraction definition (host sequences: coupling per element,
-        fuel and oxidiser compositions per species) and mapping thresholds."""
+        fuel and oxidiser compositions per species), mapping thresholds and
+        the Z band width (0: one band)."""
         import numpy as np
         c = np.ascontiguousarray(coupling, dtype=np.float64)
         yf = np.ascontiguousarray(y_fuel, dtype=np.float64)
         yo = np.ascontiguousarray(y_ox, dtype=np.float64)
         if c.shape != (self.mech.elements().shape[1],) or yf.shape != (self.ns,) or yo.shape != (self.ns,):
             raise ValueError("coupling must be [n_elements], y_fuel and y_ox [n_species]")
+        _check(lib().chem_zone_bands(self._h, 0.0))
         _check(lib().chem_zone_config(self._h, c.ctypes.data_as(_vp), yf.ctypes.data_as(_vp),
                                       yo.ctypes.data_as(_vp), float(z_max), float(t_tol)))
+        _check(lib().chem_zone_bands(self._h, float(dz)))
 
     def mixture_fraction(self, phi: torch.Tensor) -> torch.Tensor:
         n = phi.shape[0]
@@ -270,7 +274,8 @@ class Solver:
     def integrate_zonal(self, phi: torch.Tensor, dt: float, h_io: Optional[torch.Tensor] = None,
                         out: Optional[torch.Tensor] = None):
         """One chemistry step with zonal reference mapping: (Result, mapped),
-        mapped an int8 tensor (1 = took the reference's change of state)."""
+        mapped an int8 tensor (band + 1 of a cell that took its band
+        reference's change of state, 0 for an integrated cell)."""
         n = phi.shape[0]
         if phi.dim() != 2 or phi.shape[1] != self.ns + 2:
             raise ValueError("phi must be [n, %d]" % (self.ns + 2))

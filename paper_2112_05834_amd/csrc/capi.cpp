@@ -116,7 +116,8 @@ struct chem_solver {
   std::vector<int> elem;              // [ns][ne] atom counts
   bool zone_ready = false;
   double z_max = 0, t_tol = 0;
-  double* d_zone = nullptr;           // coef [ns], streams [2], reference row [ns+2]
+  double dz = 0;                      // Z band width (0: one band)
+  double* d_zone = nullptr;           // coef [ns], streams [2], reference rows [kMaxBands][ns+2]
   unsigned long long* d_zctl = nullptr;
   signed char* d_zflag = nullptr;
   int* d_zorder = nullptr;
@@ -1037,6 +1038,8 @@ int chem_zone_config(chem_solver* s, const double* coupling, const double* y_fue
   if (!s || !coupling || !y_fuel || !y_ox) return fail(CHEM_EINVAL, "chem_zone_config: null argument");
   if (!std::isfinite(z_max) || !std::isfinite(t_tol) || t_tol < 0)
     return fail(CHEM_EINVAL, "chem_zone_config: z_max and t_tol must be finite, t_tol >= 0");
+  if (s->dz > 0 && z_max / s->dz >= chemz::kMaxBands)
+    return fail(CHEM_EINVAL, "chem_zone_config: z_max / dz gives more than 64 bands");
   for (int e = 0; e < s->ne; ++e)
     if (!std::isfinite(coupling[e])) return fail(CHEM_EINVAL, "chem_zone_config: non-finite coupling");
   for (int i = 0; i < s->ns; ++i)
@@ -1047,8 +1050,8 @@ int chem_zone_config(chem_solver* s, const double* coupling, const double* y_fue
   s->zone_ready = false;       // until the new definition is in place
   const int ns = s->ns, ne = s->ne;
   if (!s->d_zone) {
-    HIP_TRY(hipMalloc(&s->d_zone, sizeof(double) * (2 * ns + 4)), "hipMalloc zone");
-    HIP_TRY(hipMalloc(&s->d_zctl, 2 * sizeof(unsigned long long)), "hipMalloc zone");
+    HIP_TRY(hipMalloc(&s->d_zone, sizeof(double) * (ns + 2 + chemz::kMaxBands * (ns + 2))), "hipMalloc zone");
+    HIP_TRY(hipMalloc(&s->d_zctl, (chemz::kMaxBands + 1) * sizeof(unsigned long long)), "hipMalloc zone");
   }
   // inputs staged in one temporary buffer: coupling, y_fuel, y_ox, counts
   std::vector<double> in(ne + 2 * ns);
@@ -1076,6 +1079,15 @@ int chem_zone_config(chem_solver* s, const double* coupling, const double* y_fue
   s->z_max = z_max;
   s->t_tol = t_tol;
   s->zone_ready = true;
+  return CHEM_OK;
+}
+
+int chem_zone_bands(chem_solver* s, double dz) {
+  if (!s) return fail(CHEM_EINVAL, "null solver");
+  if (!std::isfinite(dz) || dz < 0) return fail(CHEM_EINVAL, "chem_zone_bands: dz must be finite and >= 0");
+  if (dz > 0 && s->zone_ready && s->z_max / dz >= chemz::kMaxBands)
+    return fail(CHEM_EINVAL, "chem_zone_bands: z_max / dz gives more than 64 bands");
+  s->dz = dz;
   return CHEM_OK;
 }
 
@@ -1120,6 +1132,13 @@ int chem_integrate_zonal(chem_solver* s, int64_t n, double dt, const double* in,
   z.stash = s->d_zone + s->ns + 2;
   z.z_max = s->z_max;
   z.t_tol = s->t_tol;
+  z.dz = s->dz;
+  z.nb = 1;
+  if (s->dz > 0 && s->z_max >= 0) {
+    const double nb = std::floor(s->z_max / s->dz) + 1.0;
+    if (!(nb <= chemz::kMaxBands)) return fail(CHEM_EINVAL, "chem_integrate_zonal: more than 64 Z bands");
+    z.nb = static_cast<int>(nb);
+  }
   z.flag = mapped ? reinterpret_cast<signed char*>(mapped) : s->d_zflag;
   z.order = s->d_zorder;
   z.ctl = s->d_zctl;

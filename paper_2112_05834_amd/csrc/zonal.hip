@@ -3,11 +3,13 @@
 // - Z is Bilger's mixture fraction, a linear function of the mass fractions:
 //     beta(Y) = sum_i Y_i b_i,  b_i = (sum_e coupling_e a_{e,i}) / W_i,
 //     Z = (beta - beta_ox) / (beta_fuel - beta_ox);
-// - the zone is every cell with Z <= z_max, and its reference is the zone cell
-//   of lowest index;
-// - a zone cell within t_tol of the reference's temperature is mapped: it
-//   takes the reference's change of T and Y over the step. Every other cell
-//   is integrated.
+// - the zone is every cell with Z <= z_max. It is one band, or with a band
+//   width dz > 0 the bands b = floor(max(Z, 0) / dz), so that cells are mapped
+//   only from a reference of similar Z. Each band's reference is its cell of
+//   lowest index;
+// - a zone cell within t_tol of its band reference's temperature is mapped:
+//   it takes the reference's change of T and Y over the step. Every other
+//   cell is integrated.
 //
 // All of this is streaming work next to the integration: one thread per cell
 // or per element, except the classification, which stages rows through LDS so
@@ -52,20 +54,26 @@ __global__ void k_mixture_fraction(long long n, int ns, const double* phi, const
 }
 
 __global__ void k_zone_reset(unsigned long long* ctl) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl[0] = kNone;
-    ctl[1] = 0;
-  }
+  if (blockIdx.x == 0 && threadIdx.x < kMaxBands) ctl[threadIdx.x] = kNone;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl[kMaxBands] = 0;
 }
 
-// Zone flag of one cell, and one atomic per wave for the reference: the
-// lowest zone lane holds the wave's lowest zone cell.
+// Band flag of one cell, and one atomic per band present in the wave for the
+// references: the lowest lane of a band holds the wave's lowest cell of it.
 __device__ __forceinline__ void classify_one(const ZoneArgs& a, long long c, double z) {
   const bool zone = c < a.n && z <= a.z_max;
-  if (c < a.n) a.flag[c] = zone ? 1 : 0;
-  const unsigned long long m = __ballot(zone);
-  if (m && static_cast<unsigned long long>(__lane_id()) == static_cast<unsigned long long>(__builtin_ctzll(m)))
-    atomicMin(a.ctl, static_cast<unsigned long long>(c));
+  int band = -1;
+  if (zone) band = a.dz > 0.0 ? min(static_cast<int>(floor(fmax(z, 0.0) / a.dz)), a.nb - 1) : 0;
+  if (c < a.n) a.flag[c] = static_cast<signed char>(band + 1);
+  unsigned long long m = __ballot(zone);
+  const unsigned long long lane = static_cast<unsigned long long>(__lane_id());
+  while (m) {                       // wave-uniform loop over the bands present
+    const int lead = __builtin_ctzll(m);
+    const int b = __shfl(band, lead);
+    const unsigned long long same = __ballot(band == b);
+    if (lane == static_cast<unsigned long long>(lead)) atomicMin(a.ctl + b, static_cast<unsigned long long>(c));
+    m &= ~same;
+  }
 }
 
 // Each thread walks its own row (used above kStageMaxNs species).
@@ -135,20 +143,25 @@ __global__ void __launch_bounds__(kStageThreads) k_zone_classify_staged(ZoneArgs
 __global__ void k_zone_select(ZoneArgs a) {
   const long long c = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x;
   const int stride = a.ns + 2;
-  const unsigned long long ref = a.ctl[0];
   bool mapped = false;
   if (c < a.n) {
-    if (ref != kNone && a.flag[c] && static_cast<unsigned long long>(c) != ref)
-      mapped = fabs(a.phi_in[c * stride] - a.phi_in[static_cast<long long>(ref) * stride]) <= a.t_tol;
-    a.flag[c] = mapped ? 1 : 0;
-    if (static_cast<unsigned long long>(c) == ref)
-      for (int k = 0; k < stride; ++k) a.stash[k] = a.phi_in[c * stride + k];
+    const int b = a.flag[c] - 1;
+    if (b >= 0) {
+      // every zone band has a reference: the lowest of its cells
+      const unsigned long long ref = a.ctl[b];
+      if (static_cast<unsigned long long>(c) == ref) {
+        for (int k = 0; k < stride; ++k) a.stash[b * stride + k] = a.phi_in[c * stride + k];
+      } else {
+        mapped = fabs(a.phi_in[c * stride] - a.phi_in[static_cast<long long>(ref) * stride]) <= a.t_tol;
+      }
+    }
+    if (!mapped) a.flag[c] = 0;
   }
   const bool keep = c < a.n && !mapped;
   const unsigned long long m = __ballot(keep);
   const int lane = __lane_id();
   unsigned long long base = 0;
-  if (lane == 0 && m) base = atomicAdd(a.ctl + 1, static_cast<unsigned long long>(__popcll(m)));
+  if (lane == 0 && m) base = atomicAdd(a.ctl + kMaxBands, static_cast<unsigned long long>(__popcll(m)));
   base = __shfl(base, 0);
   if (keep) {
     const unsigned long long k = base + static_cast<unsigned long long>(__popcll(m & ((1ull << lane) - 1ull)));
@@ -159,24 +172,24 @@ __global__ void k_zone_select(ZoneArgs a) {
 // The persistent kernel pulls queue positions from head up to n: start it at
 // the first integrated cell.
 __global__ void k_zone_head(long long n, const unsigned long long* ctl, unsigned long long* head) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) head[0] = static_cast<unsigned long long>(n) - ctl[1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) head[0] = static_cast<unsigned long long>(n) - ctl[kMaxBands];
 }
 
 // One thread per element of a mapped cell's row: T and Y move by the
 // reference's change, p stays; no steps counted, the reference's status.
 __global__ void k_zone_apply(ZoneArgs a) {
-  const unsigned long long ref = a.ctl[0];
-  if (ref == kNone) return;
   const int stride = a.ns + 2;
   const long long total = a.n * stride;
-  const long long r0 = static_cast<long long>(ref) * stride;
   for (long long e = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; e < total;
        e += static_cast<long long>(gridDim.x) * blockDim.x) {
     const long long c = e / stride;
-    if (!a.flag[c]) continue;
+    const int b = a.flag[c] - 1;     // mapped cells only: their band has a reference
+    if (b < 0) continue;
+    const unsigned long long ref = a.ctl[b];
+    const long long r0 = static_cast<long long>(ref) * stride;
     const int k = static_cast<int>(e - c * stride);
     const double x = a.phi_in[e];
-    a.phi_out[e] = k == 1 ? x : x + (a.phi_out[r0 + k] - a.stash[k]);
+    a.phi_out[e] = k == 1 ? x : x + (a.phi_out[r0 + k] - a.stash[b * stride + k]);
     if (k == 0) {
       if (a.n_acc) a.n_acc[c] = 0;
       if (a.n_rej) a.n_rej[c] = 0;

@@ -7,6 +7,8 @@
 
 namespace chemz {
 
+constexpr int kMaxBands = 64;       // Z bands of one zone, each with its own reference
+
 struct ZoneArgs {
   long long n;                 // cells
   int ns;                      // species; a cell's row holds ns + 2 doubles
@@ -15,11 +17,13 @@ struct ZoneArgs {
   const double* coef;          // [ns] Bilger coefficient b_i of each species
   const double* streams;       // [2] beta of the fuel and of the oxidiser stream
   double z_max, t_tol;
-  signed char* flag;           // [n] zone candidate, then 1 = mapped, 0 = integrated
+  double dz;                   // band width (0: the whole zone is one band)
+  int nb;                      // bands: 1, or floor(z_max / dz) + 1 <= kMaxBands
+  signed char* flag;           // [n] band + 1 of a zone cell, then band + 1 if mapped, 0 if integrated
   int* order;                  // [n] queue order; integrated cells fill its tail
-  unsigned long long* ctl;     // [0] reference cell (~0 = none), [1] integrated cells
+  unsigned long long* ctl;     // [b] reference cell of band b (~0 = none), [kMaxBands] integrated cells
   unsigned long long* head;    // queue head of the persistent integration kernel
-  double* stash;               // [ns + 2] the reference cell's input row
+  double* stash;               // [kMaxBands][ns + 2] each band's reference input row
   int* n_acc;                  // the caller's counters and status (NULL allowed)
   int* n_rej;
   signed char* status;
@@ -33,8 +37,8 @@ hipError_t launch_zone_setup(int ns, int ne, const double* coupling, const int* 
 // z[c] = (beta(Y_c) - beta_ox) / (beta_fuel - beta_ox) for n cells.
 hipError_t launch_mixture_fraction(long long n, int ns, const double* phi, const double* coef,
                                    const double* streams, double* z, hipStream_t st);
-// Resets ctl, marks the zone (Z <= z_max) in flag and finds the reference
-// (the zone cell of lowest index).
+// Resets ctl, marks each zone cell (Z <= z_max) with its band in flag and
+// finds each band's reference (its cell of lowest index).
 hipError_t launch_zone_classify(const ZoneArgs& a, hipStream_t st);
 // Final mapped flags; the integrated cells go to the tail of order, the queue
 // head is set to the first of them and the reference's input row is kept.

@@ -73,6 +73,7 @@ def test_null_and_bad_arguments_are_errors_not_crashes():
     assert L.chem_autotune_cached(None, b"/tmp/x.jsonl", 1, None, 1e-6, None, ctypes.byref(n)) == -1
     assert L.chem_zone_config(None, None, None, None, 0.0, 0.0) == -1
     assert L.chem_mixture_fraction(None, 1, None, None, None) == -1
+    assert L.chem_zone_bands(None, 0.1) == -1
     assert L.chem_integrate_zonal(None, 1, 1e-6, None, None, None, None, None, None, None, None) == -1
     assert L.chem_mech_elements(None, ctypes.byref(n), None) == -1
     assert L.chem_last_error()          # a message is set

@@ -35,11 +35,28 @@ def _states(mech_name, n, d, pressure=6.0e6, seed=106):
     return mech, path, synth.generate_states(mech, n, pressure, "ambient", seed)
 
 
-def _solver(path, mech, z_max=Z_MAX, t_tol=T_TOL, **kw):
+def _solver(path, mech, z_max=Z_MAX, t_tol=T_TOL, dz=0.0, **kw):
     S = chem.Solver(chem.Mechanism(path), chem.default_opts(schedule=chem.PERSISTENT, **kw))
     c, yf, yo = synth.bilger_streams(mech)
-    S.zone_config(c, yf, yo, z_max, t_tol)
+    S.zone_config(c, yf, yo, z_max, t_tol, dz=dz)
     return S
+
+
+def _rule_bands(z, T, z_max, t_tol, dz):
+    """The banded mapping rule written out on the host from the oracle's Z:
+    (band + 1 of mapped cells else 0, reference cell of each zone cell)."""
+    n = len(z)
+    zone = np.nonzero(z <= z_max)[0]
+    band = np.floor(np.maximum(z[zone], 0.0) / dz).astype(np.int64) if dz > 0 else np.zeros(len(zone), np.int64)
+    _, first = np.unique(band, return_index=True)          # first occurrence in index order
+    refcell = dict(zip(band[first], zone[first]))
+    ref = np.array([refcell[b] for b in band], dtype=np.int64)
+    mapped = np.zeros(n, dtype=np.int8)
+    hit = (zone != ref) & (np.abs(T[zone] - T[ref]) <= t_tol)
+    mapped[zone[hit]] = band[hit] + 1
+    refs = np.full(n, -1, dtype=np.int64)
+    refs[zone] = ref
+    return mapped, refs
 
 
 def _np(r):
@@ -113,6 +130,61 @@ def test_zonal_against_oracle(tmp_path, mech_name, n):
     assert np.array_equal(out[:, 1], phi[:, 1])
     ref = int(np.nonzero(O.Mech(path).mixture_fraction(c, yf, yo, phi) <= Z_MAX)[0][0])
     _check_mapped(phi, out, mapped, ref, na, nr, st)
+
+
+def test_zonal_bands_against_oracle(tmp_path):
+    """Z bands (dz = 0.01 up to z_max = 0.3): the unburnt and hot cells of
+    the spray recipe fall into 31 bands, each mapped from its own reference."""
+    mech, path, phi = _states("spray54", 400, str(tmp_path))
+    S = _solver(path, mech, z_max=0.3, t_tol=5.0, dz=0.01)
+    r, m = S.integrate_zonal(_to(phi), 1e-6)
+    out, h, na, nr, st = _np(r)
+    mapped = m.cpu().numpy()
+    c, yf, yo = synth.bilger_streams(mech)
+    o_out, o_h, o_na, o_nr, o_st, o_mapped = O.Mech(path).integrate_zonal(
+        phi, 1e-6, c, yf, yo, 0.3, 5.0, dz=0.01, n_threads=NCPU)
+    assert np.array_equal(mapped, o_mapped)
+    assert len(np.unique(mapped[mapped > 0])) >= 3          # several bands map cells
+    assert np.array_equal(st, o_st)
+    solved = mapped == 0
+    same = (na[solved] == o_na[solved]) & (nr[solved] == o_nr[solved])
+    _compare_integrated(out[solved], o_out[solved], same)
+    z = O.Mech(path).mixture_fraction(c, yf, yo, phi)
+    want, refs = _rule_bands(z, phi[:, 0], 0.3, 5.0, 0.01)
+    assert np.array_equal(mapped, want)
+    for i in np.nonzero(mapped)[0]:
+        ref = refs[i]
+        assert np.array_equal(out[i, 2:], phi[i, 2:] + (out[ref, 2:] - phi[ref, 2:]))
+        assert out[i, 0] == phi[i, 0] + (out[ref, 0] - phi[ref, 0])
+        assert na[i] == 0 and st[i] == st[ref]
+
+
+def test_zonal_bands_full_size_headline_cells(tmp_path):
+    """The headline spray cells (262 144) with 60 Z bands up to z_max = 0.3:
+    flags as the host rule on the oracle's Z, integrated cells identical to
+    chem_integrate, mapped cells their band reference's change exactly."""
+    wl, mech, path, phi = synth.workload_inputs("spray54_262144", str(tmp_path))
+    S = _solver(path, mech, z_max=0.3, t_tol=2.0, dz=0.005)
+    x = _to(phi)
+    r, m = S.integrate_zonal(x, wl.dt)
+    rz = _np(r)
+    mapped = m.cpu().numpy()
+    rp = _np(S.integrate(x, wl.dt))
+    c, yf, yo = synth.bilger_streams(mech)
+    z = O.Mech(path).mixture_fraction(c, yf, yo, phi)
+    want, refs = _rule_bands(z, phi[:, 0], 0.3, 2.0, 0.005)
+    assert np.array_equal(mapped, want)
+    solved = mapped == 0
+    for a, b in zip(rz, rp):
+        assert np.array_equal(a[solved], b[solved])
+    out = rz[0]
+    idx = np.nonzero(mapped)[0]
+    rr = refs[idx]
+    assert np.array_equal(out[idx, 2:], phi[idx, 2:] + (out[rr, 2:] - phi[rr, 2:]))
+    assert np.array_equal(out[idx, 0], phi[idx, 0] + (out[rr, 0] - phi[rr, 0]))
+    dT = np.abs(out[idx, 0] - rp[0][idx, 0])
+    print("bands: %.1f%% mapped in %d bands, max |T_mapped - T_integrated| = %.3e K"
+          % (100 * (mapped > 0).mean(), len(np.unique(mapped[mapped > 0])), dT.max()), flush=True)
 
 
 def test_zone_boundary_is_decided_in_the_same_bits(tmp_path):
@@ -307,3 +379,8 @@ def test_zone_config_errors(tmp_path):
         S.zone_config(c, yf, yo, Z_MAX, -1.0)
     with pytest.raises(chem.ChemError):
         S.zone_config(c, yf, yo, float("nan"), T_TOL)
+    # bands: a negative width, and more than 64 bands for z_max
+    with pytest.raises(chem.ChemError):
+        S.zone_config(c, yf, yo, 0.3, T_TOL, dz=-0.01)
+    with pytest.raises(chem.ChemError):
+        S.zone_config(c, yf, yo, 0.3, T_TOL, dz=0.001)

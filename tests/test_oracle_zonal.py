@@ -133,8 +133,8 @@ def test_zonal_reference_is_the_first_zone_cell_and_t_tol_is_inclusive(tmp_path)
     z = M.mixture_fraction(c, yf, yo, phi)
     assert set(np.nonzero(z <= 1e-6)[0]) == {3, 5, 7, 9}
     assert list(np.nonzero(mapped)[0]) == [5, 7]          # 3 is the reference, 9 is 2.5 K away
-    solved = M.integrate(phi[~mapped], wl.dt)
-    assert np.array_equal(out[~mapped], solved[0])
+    solved = M.integrate(phi[mapped == 0], wl.dt)
+    assert np.array_equal(out[mapped == 0], solved[0])
     for i in (5, 7):
         assert np.array_equal(out[i, 2:], phi[i, 2:] + (out[3, 2:] - phi[3, 2:]))
         assert out[i, 0] == phi[i, 0] + (out[3, 0] - phi[3, 0]) and out[i, 1] == phi[i, 1]
@@ -145,3 +145,35 @@ def test_zonal_reference_is_the_first_zone_cell_and_t_tol_is_inclusive(tmp_path)
     assert mapped2[5]
     direct = M.integrate(phi[5:6], wl.dt)[0][0]
     assert np.allclose(out2[5], direct, rtol=1e-14, atol=1e-20)
+
+
+def test_zonal_bands_each_have_their_own_reference(tmp_path):
+    """Two Z bands (dz = 0.05): air cells (Z ~ 0) and cells of a fuel blend at
+    Z ~ 0.12, each band mapped from its own first cell, with every other cell
+    fuel-rich (Z ~ 0.5, outside the zone); a band width above z_max is the
+    single band of dz = 0."""
+    wl, M, c, yf, yo, phi = _zonal_case(tmp_path)
+    air = np.full(phi.shape[1] - 2, 1e-12) + yo
+    air /= air.sum()
+    blend = 0.12 * yf + 0.88 * yo + 1e-12
+    blend /= blend.sum()
+    rich = 0.5 * yf + 0.5 * yo + 1e-12
+    rich /= rich.sum()
+    comp = {i: rich for i in range(phi.shape[0])}
+    comp.update({2: air, 4: blend, 6: air, 8: blend, 10: blend})
+    for i, y in comp.items():
+        phi[i, 2:] = y
+        phi[i, 0] = 1200.0 + 0.1 * i
+    z = M.mixture_fraction(c, yf, yo, phi)
+    assert z[2] < 1e-6 and 0.1 < z[4] < 0.15 and (z[[0, 1, 3, 5, 7, 9, 11]] > 0.4).all()
+    out, h, na, nr, st, mapped = M.integrate_zonal(phi, wl.dt, c, yf, yo, z_max=0.2, t_tol=2.0, dz=0.05)
+    band4 = int(np.floor(z[4] / 0.05)) + 1
+    assert list(mapped) == [0, 0, 0, 0, 0, 0, 1, 0, band4, 0, band4, 0]
+    for i, ref in ((6, 2), (8, 4), (10, 4)):
+        assert np.array_equal(out[i, 2:], phi[i, 2:] + (out[ref, 2:] - phi[ref, 2:]))
+        assert out[i, 0] == phi[i, 0] + (out[ref, 0] - phi[ref, 0])
+    # one band over the same zone: every zone cell maps from cell 2
+    one = M.integrate_zonal(phi, wl.dt, c, yf, yo, z_max=0.2, t_tol=2.0, dz=0.0)
+    assert list(np.nonzero(one[5])[0]) == [4, 6, 8, 10]
+    wide = M.integrate_zonal(phi, wl.dt, c, yf, yo, z_max=0.2, t_tol=2.0, dz=1.0)
+    assert np.array_equal(wide[5], one[5]) and np.array_equal(wide[0], one[0])
