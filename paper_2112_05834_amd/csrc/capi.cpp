@@ -1049,7 +1049,11 @@ int chem_zone_config(chem_solver* s, const double* coupling, const double* y_fue
   HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
   s->zone_ready = false;       // until the new definition is in place
   const int ns = s->ns, ne = s->ne;
-  if (!s->d_zone) {
+  if (!s->d_zone || !s->d_zctl) {    // both, or (after a failed allocation) again
+    hipFree(s->d_zone);
+    hipFree(s->d_zctl);
+    s->d_zone = nullptr;
+    s->d_zctl = nullptr;
     HIP_TRY(hipMalloc(&s->d_zone, sizeof(double) * (ns + 2 + chemz::kMaxBands * (ns + 2))), "hipMalloc zone");
     HIP_TRY(hipMalloc(&s->d_zctl, (chemz::kMaxBands + 1) * sizeof(unsigned long long)), "hipMalloc zone");
   }
