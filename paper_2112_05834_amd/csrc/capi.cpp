@@ -202,7 +202,9 @@ int chem_solver_create(const chem_mech* m, const chem_opts* o, int32_t dev, chem
   int ndev = 0;
   HIP_TRY(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
   if (dev < 0 || dev >= ndev) return fail(CHEM_EINVAL, "hip_device out of range");
-  auto s = std::make_unique<chem_solver>();
+  // handed to the caller on success; on any error below, freed together with
+  // the device memory allocated so far
+  std::unique_ptr<chem_solver, void (*)(chem_solver*)> s(new chem_solver(), chem_solver_free);
   s->dev = dev;
   s->opts = *o;
   s->ns = m->host.ns;
