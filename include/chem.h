@@ -49,7 +49,7 @@ extern "C" {
 #define CHEM_CELL_OK 0
 #define CHEM_CELL_MAX_STEPS 1   /* attempted steps reached opts.max_steps     */
 #define CHEM_CELL_H_UNDERFLOW 2 /* step size fell below 1e-20 s               */
-#define CHEM_CELL_NONFINITE 3   /* non-finite input (T, p or a Y)             */
+#define CHEM_CELL_NONFINITE 3   /* non-finite input (T, p or a Y), or p <= 0  */
 #define CHEM_CELL_SINGULAR 4    /* exact zero pivot in the LU of M            */
 #define CHEM_CELL_T_RANGE 5     /* an accepted step left T in [200, 6000] K   */
 
@@ -73,19 +73,27 @@ typedef struct {
   int64_t hbm_budget_bytes; /* workspace budget for in-flight cells; 0 = 50% of free     */
 } chem_opts;
 
-/* Fill o with the defaults above. */
+/* Fill o with the defaults above. Paper: Results and discussion (the Spray A
+ * run's tolerances, atol 1e-10 and rtol 1e-6, are the defaults). */
 void chem_opts_default(chem_opts* o);
 
 /* ---- mechanism ---------------------------------------------------------- */
 
-/* Parse the text mechanism at path (format: species with W and NASA-7
+/* Paper: Introduction (the kinetics ODE f of a given mechanism) and
+ * Methodology, Analytical Jacobian paragraph (rates and Jacobian generated
+ * for a given chemical kinetics mechanism).
+ * Parse the text mechanism at path (format: species with W and NASA-7
  * coefficients, reactions with Arrhenius A [SI], b, Ea [J/mol], optional
  * third-body efficiencies and Troe parameters). Host only. *out is owned by
  * the caller and released with chem_mech_free. Errors: CHEM_EINVAL,
  * CHEM_EMECH (message names the offending token). */
 int chem_mech_load(const char* path, chem_mech** out);
+/* Species and reaction counts (n = Ns + 1 state components). Paper: Results
+ * and discussion (the 54-species, 269-reaction mechanism). */
 int chem_mech_dims(const chem_mech* m, int32_t* n_species, int32_t* n_reactions);
-/* Algorithmic work per evaluation, counted from the mechanism's structure:
+/* Paper: Methodology, Analytical Jacobian paragraph and Fig. 2 (the cost of
+ * right-hand side and Jacobian evaluations per cell).
+ * Algorithmic work per evaluation, counted from the mechanism's structure:
  * flops of one right-hand side and of one analytical Jacobian (beyond the
  * right-hand side it also yields), with each exp/log/pow counted as one
  * transcendental (reported separately, not in the flop figures). Any output
@@ -96,7 +104,9 @@ void chem_mech_free(chem_mech* m); /* NULL-safe */
 
 /* ---- solver ------------------------------------------------------------- */
 
-/* Bind a mechanism to HIP device hip_device: uploads the mechanism image
+/* Paper: Methodology, Analytical Jacobian paragraph (the per-cell stiff ODE
+ * solver, its tolerances and its linear algebra).
+ * Bind a mechanism to HIP device hip_device: uploads the mechanism image
  * (the part staged in LDS by every block plus thermo tables) and allocates the
  * queue and scratch. The mechanism may be freed afterwards. Errors:
  * CHEM_EINVAL, CHEM_EHIP, CHEM_ENOMEM, CHEM_EUNSUPPORTED (state size n = Ns+1
@@ -104,11 +114,16 @@ void chem_mech_free(chem_mech* m); /* NULL-safe */
 int chem_solver_create(const chem_mech* m, const chem_opts* o, int32_t hip_device,
                        chem_solver** out);
 void chem_solver_free(chem_solver* s); /* NULL-safe; synchronises the device */
-/* Replace the solver's options (same validation as create). */
+/* Replace or read the solver's options (same validation as create). Paper:
+ * Methodology, Analytical Jacobian paragraph and Fig. 2 (solver tolerances). */
 int chem_solver_set_opts(chem_solver* s, const chem_opts* o);
 int chem_solver_get_opts(const chem_solver* s, chem_opts* o);
 
-/* Integrate every cell over [0, dt] (one chemistry step).
+/* Paper: Introduction (phi = (p, T, species) advanced by f = dphi/dt) and
+ * Methodology, Analytical Jacobian paragraph (implicit integration with the
+ * analytical J, LU decomposition and back substitution); the schedules serve
+ * Methodology, DLBFoam paragraph (balancing the uneven per-cell cost).
+ * Integrate every cell over [0, dt] (one chemistry step).
  *   phi_in, phi_out : device, [n_cells][2+Ns] float64 = (T [K], p [Pa], Y_1..Y_Ns);
  *                     phi_out may alias phi_in exactly (not partially).
  *   h_io   : device [n_cells] float64 or NULL. In: first substep (<= 0 means
@@ -127,7 +142,9 @@ int chem_integrate(chem_solver* s, int64_t n_cells, double dt, const double* phi
                    double* phi_out, double* h_io, int32_t* n_acc, int32_t* n_rej,
                    int8_t* status, void* stream);
 
-/* n_steps chained chemistry steps of the same dt, each feeding the next (h_io
+/* Paper: Results and discussion (chemistry is solved in every CFD iteration;
+ * the Spray A run times 100 of them).
+ * n_steps chained chemistry steps of the same dt, each feeding the next (h_io
  * carried between them), captured once into a HIP graph and replayed; phi_out
  * holds the final state, n_acc / n_rej accumulate over the steps and status is
  * the first non-zero status of the steps. phi_in is not modified; the library
@@ -142,12 +159,16 @@ int chem_integrate_steps(chem_solver* s, int32_t n_steps, int64_t n_cells, doubl
 
 /* ---- kernel-level entry points (tests and roofline measurements) -------- */
 
-/* Right-hand side f(y) and analytical Jacobian at every cell's state.
+/* Paper: Methodology, Analytical Jacobian paragraph: the right-hand side
+ * (reaction rate evaluations) and J_ij = df_i/dphi_j.
+ * Right-hand side f(y) and analytical Jacobian at every cell's state.
  *   phi : device [n_cells][2+Ns]; f : device [n_cells][n] (n = Ns+1, order
  *   T, Y_1..Y_Ns); J : device [n_cells][n][n] row-major (df_i/dy_j) or NULL. */
 int chem_eval_rhs_jac(chem_solver* s, int64_t n_cells, const double* phi, double* f, double* J,
                       void* stream);
-/* Batched LU with partial pivoting (LAPACK getrf semantics: piv[k] is the row
+/* Paper: Methodology, Analytical Jacobian paragraph: the LU decomposition and
+ * back substitution of the integrator (LAPACK routines in the paper).
+ * Batched LU with partial pivoting (LAPACK getrf semantics: piv[k] is the row
  * swapped with row k at step k, 0-based; ties go to the lowest row) of
  * row-major n x n matrices A[batch][n][n], in place; info[b] = 0 or k+1 for
  * the first exactly-zero pivot. Then, if b is not NULL, solves A x = b for
@@ -156,6 +177,10 @@ int chem_lu_batch(chem_solver* s, int64_t batch, double* A, int32_t* piv, int32_
                   double* b, void* stream);
 
 /* ---- learned cost model (changes scheduling only, never results) ------- */
+/* Paper for every call of this block: Methodology, DLBFoam paragraph (a
+ * cell's cost depends on its local thermochemical state; problems move from
+ * busy to idle workers). Here a model predicts the cost so that the queue
+ * hands out the costliest cells first. */
 
 /* Keep a device log of (features[4], ln substeps) per integrated cell, up to
  * capacity records (ring; later records overwrite). capacity 0 disables. */
@@ -254,7 +279,9 @@ int chem_autotune(chem_solver* s, int64_t n_sample, const double* phi_sample_dev
 int chem_autotune_cached(chem_solver* s, const char* cache_path, int64_t n_sample, const double* phi_sample_dev,
                          double dt, void* stream, int32_t* from_cache);
 
-/* Workspace of the workgroup-per-cell path (state sizes above 64): number of
+/* Paper: Methodology, Analytical Jacobian paragraph (the dense Jacobian and
+ * its LU, here kept in HBM for large mechanisms).
+ * Workspace of the workgroup-per-cell path (state sizes above 64): number of
  * HBM slots (cells in flight; one per resident workgroup, at most
  * hbm_budget_bytes in total, default half the free device memory) and bytes
  * per slot (J and M, 2 n ld doubles with ld = n rounded up to 16). Allocates
@@ -268,9 +295,12 @@ int chem_workspace_info(chem_solver* s, int32_t* slots, int64_t* bytes_per_slot)
  * fraction Z. Read here as:
  *   beta(Y) = sum_i Y_i / W_i * sum_e coupling[e] a_{e,i}  (a = atom counts),
  *   Z = (beta(Y) - beta(y_ox)) / (beta(y_fuel) - beta(y_ox));
- * the zone is every cell with Z <= z_max, and its reference is the zone cell
- * of lowest index. A zone cell whose |T - T_ref| <= t_tol is mapped: it takes
- * the reference's change of T and of every Y over the step (p kept). */
+ * the zone is every cell with Z <= z_max, split into Z bands of width dz
+ * (chem_zone_bands; one band by default), and each band's reference is its
+ * zone cell of lowest index. A zone cell whose |T - T_ref| <= t_tol for its
+ * band's reference is mapped: it takes that reference's change of T and of
+ * every Y over the step (p kept). Every call of this block cites this
+ * passage. */
 
 /* Number of elements of the mechanism and, if counts is not NULL, the atom
  * counts of every species: host int32 [Ns][n_elements], row-major. */
@@ -320,6 +350,8 @@ int chem_integrate_zonal(chem_solver* s, int64_t n_cells, double dt, const doubl
                          void* stream);
 
 /* ---- kernel timing ---------------------------------------------------- */
+/* Paper: Fig. 2 and Results and discussion (evaluation and CPU times of the
+ * chemistry solution), measured here per integration launch. */
 
 /* enable != 0: from now on record a pair of HIP events on the caller's
  * stream around every integration-kernel launch made outside graph capture
@@ -330,6 +362,8 @@ int chem_kernel_timing(chem_solver* s, int32_t enable);
  * records are cleared. */
 int chem_kernel_times(chem_solver* s, float* ms_out, int32_t cap, int32_t* n_out);
 
+/* Message of the last failing call on this thread (utility; no paper
+ * passage). */
 const char* chem_last_error(void);
 
 #ifdef __cplusplus

@@ -1090,9 +1090,16 @@ int chem_zone_config(chem_solver* s, const double* coupling, const double* y_fue
 
 int chem_zone_bands(chem_solver* s, double dz) {
   if (!s) return fail(CHEM_EINVAL, "null solver");
-  if (!std::isfinite(dz) || dz < 0) return fail(CHEM_EINVAL, "chem_zone_bands: dz must be finite and >= 0");
-  if (dz > 0 && s->zone_ready && s->z_max / dz >= chemz::kMaxBands)
+  // a rejected band width leaves no zone definition behind (a zone left
+  // live with its earlier width would map across the whole of Z <= z_max)
+  if (!std::isfinite(dz) || dz < 0) {
+    s->zone_ready = false;
+    return fail(CHEM_EINVAL, "chem_zone_bands: dz must be finite and >= 0");
+  }
+  if (dz > 0 && s->zone_ready && s->z_max / dz >= chemz::kMaxBands) {
+    s->zone_ready = false;
     return fail(CHEM_EINVAL, "chem_zone_bands: z_max / dz gives more than 64 bands");
+  }
   s->dz = dz;
   return CHEM_OK;
 }

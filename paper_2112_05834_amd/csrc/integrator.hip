@@ -604,7 +604,8 @@ struct Cell {
     int pos;
     double rdiag;
     int status = 0;
-    if (Gp::any((valid && !isfinite(y)) || !isfinite(p))) status = 3;
+    // a non-finite state, or a pressure that is not a positive number
+    if (Gp::any((valid && !isfinite(y)) || !isfinite(p) || !(p > 0.0))) status = 3;
     double h = hio > 0.0 ? hio : dt;
     double hnext = h, t = 0.0;
     int nacc = 0, nrej = 0, att = 0, consec = 0;

@@ -508,7 +508,7 @@ __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, 
   const int n = A.ns + 1;
   const int t = threadIdx.x;
   int status = 0;
-  const bool bad = (t < n && !isfinite(W.y[t])) || !isfinite(p);
+  const bool bad = (t < n && !isfinite(W.y[t])) || !isfinite(p) || !(p > 0.0);
   if (__syncthreads_or(bad)) status = 3;
   double h = hio > 0.0 ? hio : dt;
   double hnext = h, tt = 0.0;

@@ -114,3 +114,35 @@ def troe_mix(seed=5):
         synth.Reaction(synth.ELEMENTARY, True, [(0, 1), (3, 1)], [(4, 1), (1, 1)], 2e13 * 1e-6, 0.0, 3e4),
     ]
     return _mech(comps, nasa, rx)
+
+
+def third_body_efficiencies(A=1.0e2, alpha_zero=2, alpha_three=3):
+    """A + B + M -> C + M (species 0..3) with efficiency 0 for species
+    alpha_zero and 3 for species alpha_three, all others 1:
+    [M] = p/(RT) - C_k + 2 C_k' exactly."""
+    n = [_nasa(h=-100.0 * i) for i in range(4)]
+    rx = [synth.Reaction(synth.THIRD_BODY, False, [(0, 1), (1, 1)], [(2, 1)], A, 0.0, 0.0,
+                         eff=[(alpha_zero, 0.0), (alpha_three, 3.0)])]
+    return _mech([(1, 0, 0, 0), (0, 0, 1, 0), (1, 0, 1, 0), (0, 0, 0, 2)], n, rx)
+
+
+def troe_general(A=3.0e6, b=0.7, Ea=2.2e4, A0=5.0e3, b0=-1.3, Ea0=9.0e3,
+                 a=0.62, T3=170.0, T1=1900.0, T2=4300.0, eff=((2, 0.0), (3, 3.0))):
+    """A + B (+M) -> C with every Troe parameter active (a, T3, T1, T2), both
+    rate constants of modified-Arrhenius form with b != 0 and Ea != 0, and
+    non-unit efficiencies; irreversible, so q = k_inf Pr/(1+Pr) F C_A C_B."""
+    n = [_nasa(h=-100.0 * i) for i in range(4)]
+    rx = [synth.Reaction(synth.TROE, False, [(0, 1), (1, 1)], [(2, 1)], A, b, Ea, eff=list(eff),
+                         troe=(A0, b0, Ea0, a, T3, T1, T2, 1.0))]
+    return _mech([(1, 0, 0, 0), (0, 0, 1, 0), (1, 0, 1, 0), (0, 0, 0, 2)], n, rx)
+
+
+def arrhenius_isomer(A=4.0e9, b=1.7, Ea=8.5e4, a7_shift=0.45):
+    """A <=> B isomers (equal W, equal NASA coefficients except a7) with a
+    modified-Arrhenius forward rate: ln kf = ln A + b ln T - (Ea/R)/T and,
+    since Kc = exp(a7_B - a7_A) does not depend on T, ln kr = ln kf - a7_shift."""
+    nA = _nasa(h=-1000.0, s=25.0)
+    nB = nA.copy()
+    nB[6] += a7_shift
+    rx = [synth.Reaction(synth.ELEMENTARY, True, [(0, 1)], [(1, 1)], A, b, Ea)]
+    return _mech([(1, 1, 1, 0), (1, 1, 1, 0)], [nA, nB], rx, names=["A", "B"])

@@ -147,18 +147,19 @@ def test_integrate_tiny_all_cells(tiny):
 
 def test_integrate_spray_full_size_sampled(spray):
     """Config at full size (262144 cells, one launch) on the GPU; a seeded
-    sample of cells is recomputed by the oracle one by one."""
+    sample of 1024 cells is recomputed by the oracle one by one. At most one
+    of them (0.1%) may take another step sequence."""
     wl, mech, path, phi = spray
     S = chem.Solver(chem.Mechanism(path), device=0)
     r = S.integrate(_to(phi), wl.dt)
     torch.cuda.synchronize()
-    idx = synth.sample_indices(phi.shape[0], 192, 4)
+    idx = synth.sample_indices(phi.shape[0], 1024, 4)
     ref, h, na, nr, st = O.Mech(path).integrate(phi[idx], wl.dt, n_threads=NCPU)
     gst = r.status.cpu().numpy()
     assert np.array_equal(gst[idx], st)
     assert (gst == 0).all()
     _compare(phi[idx], r.phi.cpu().numpy()[idx], ref,
-             (r.n_acc.cpu().numpy()[idx], r.n_rej.cpu().numpy()[idx]), (na, nr), frac_diff=0.02)
+             (r.n_acc.cpu().numpy()[idx], r.n_rej.cpu().numpy()[idx]), (na, nr))
     eq = (r.n_acc.cpu().numpy()[idx] == na) & (r.n_rej.cpu().numpy()[idx] == nr)
     _compare_h(r.h.cpu().numpy()[idx], h, eq, "spray")
     out = r.phi.cpu().numpy()
@@ -178,11 +179,11 @@ def test_spray_shear_layer_tolerances_sampled(spray):
     S = chem.Solver(chem.Mechanism(path), chem.default_opts(schedule=chem.PERSISTENT, rtol=1e-5, atol=1e-8))
     r = S.integrate(_to(phi), wl.dt)
     torch.cuda.synchronize()
-    idx = synth.sample_indices(phi.shape[0], 96, 23)
+    idx = synth.sample_indices(phi.shape[0], 1024, 23)
     ref = O.Mech(path).integrate(phi[idx], wl.dt, rtol=1e-5, atol=1e-8, n_threads=NCPU)
     na, nr = r.n_acc.cpu().numpy()[idx], r.n_rej.cpu().numpy()[idx]
     assert np.array_equal(r.status.cpu().numpy()[idx], ref[4])
-    _compare(phi[idx], r.phi.cpu().numpy()[idx], ref[0], (na, nr), (ref[2], ref[3]), frac_diff=0.02)
+    _compare(phi[idx], r.phi.cpu().numpy()[idx], ref[0], (na, nr), (ref[2], ref[3]))
     # fewer substeps than at the default tolerances on the same cells
     base = O.Mech(path).integrate(phi[idx], wl.dt, n_threads=NCPU)
     assert (ref[2] + ref[3]).sum() < (base[2] + base[3]).sum()
@@ -190,10 +191,11 @@ def test_spray_shear_layer_tolerances_sampled(spray):
 
 def test_heavytail_chained_full_size_sampled(heavy):
     """1 048 576 heavy-tailed cells, ten chained steps captured in one HIP
-    graph on the persistent queue with 4 waves per block and chunk 1: 40
+    graph on the persistent queue with 4 waves per block and chunk 1: 256
     random cells and the 8 costliest against the oracle stepping ten times
     with the step size carried over. A cell's counters are summed over the
-    ten steps, so up to 5% of the sample may differ in them."""
+    ten steps; at most one sampled cell (0.1% rounded up) may differ in
+    them."""
     wl, mech, path, phi = heavy
     S = chem.Solver(chem.Mechanism(path), chem.default_opts(schedule=chem.PERSISTENT, waves_per_block=4,
                                                            queue_chunk=1), device=0)
@@ -204,7 +206,7 @@ def test_heavytail_chained_full_size_sampled(heavy):
     gna, gnr, gst = r.n_acc.cpu().numpy(), r.n_rej.cpu().numpy(), r.status.cpu().numpy()
     assert (gst == 0).all()
     top = np.argsort(gna + gnr, kind="stable")[-8:]
-    idx = np.unique(np.concatenate([synth.sample_indices(phi.shape[0], 40, 7), top]))
+    idx = np.unique(np.concatenate([synth.sample_indices(phi.shape[0], 256, 7), top]))
     M = O.Mech(path)
     cur, hh = phi[idx].copy(), np.zeros(len(idx))
     na, nr = np.zeros(len(idx), dtype=np.int64), np.zeros(len(idx), dtype=np.int64)
@@ -214,7 +216,7 @@ def test_heavytail_chained_full_size_sampled(heavy):
         na += a
         nr += b
     out = r.phi.cpu().numpy()
-    same = _compare(phi[idx], out[idx], cur, (gna[idx], gnr[idx]), (na, nr), frac_diff=0.05)
+    same = _compare(phi[idx], out[idx], cur, (gna[idx], gnr[idx]), (na, nr))
     _compare_h(h.cpu().numpy()[idx], hh, (gna[idx] == na) & (gnr[idx] == nr), "heavytail")
     print("heavytail: %d/%d sampled cells with identical counts; substeps of the costliest %s"
           % (same, len(idx), (gna + gnr)[top].tolist()))
@@ -289,14 +291,18 @@ def test_edge_cases(tiny):
     torch.cuda.synchronize()
     assert torch.equal(x, r64.phi)
     # non-finite input and T out of range
-    bad = phi[:4].copy()
+    bad = phi[:6].copy()
     bad[0, 3] = np.nan
     bad[1, 0] = 199.0
     bad[1, 2:] = 0.0
     bad[1, 2 + mech.inert] = 1.0
+    bad[3, 1] = 0.0          # pressure not positive
+    bad[4, 1] = -1.0e5
     rb = _run(S, _to(bad), wl.dt)
     st = rb.status.cpu().numpy()
     assert st[0] == chem.CELL_NONFINITE and st[1] == chem.CELL_T_RANGE and st[2] == 0
+    assert st[3] == chem.CELL_NONFINITE and st[4] == chem.CELL_NONFINITE and st[5] == 0
+    assert np.array_equal(st, O.Mech(path).integrate(bad, wl.dt)[4])
     assert rb.phi[1, 0].item() == 199.0
     # max_steps = 1
     S.set_opts(chem.default_opts(max_steps=1))
@@ -311,6 +317,31 @@ def test_edge_cases(tiny):
     rc = chem.lib().chem_integrate(S._h, 4, 1e-6, chem.ctypes.c_void_p(y.data_ptr()),
                                    chem.ctypes.c_void_p(y[1:].data_ptr()), None, None, None, None, None)
     assert rc == -1    # partial overlap of phi_in and phi_out
+
+
+def test_status_h_underflow_matches_oracle(tiny):
+    """Status 2: with rtol = atol = 1e-300 every trial step is rejected (its
+    error estimate is far above 1, or overflows, which also counts as a
+    rejection), the substep shrinks by 0.2 and then 0.1 per attempt and falls
+    below 1e-20 s. The cell keeps its input state; status, counters and the
+    final substep equal the oracle's."""
+    wl, mech, path, phi = tiny
+    x = phi[:64]
+    S = chem.Solver(chem.Mechanism(path), chem.default_opts(rtol=1e-300, atol=1e-300), device=0)
+    r = _run(S, _to(x), wl.dt)
+    ref, h, na, nr, st = O.Mech(path).integrate(x, wl.dt, rtol=1e-300, atol=1e-300)
+    gst = r.status.cpu().numpy()
+    assert (st == chem.CELL_H_UNDERFLOW).all()
+    assert np.array_equal(gst, st)
+    assert np.array_equal(r.n_acc.cpu().numpy(), na) and np.array_equal(r.n_rej.cpu().numpy(), nr)
+    assert (na == 0).all() and (nr > 0).all()
+    assert np.array_equal(r.phi.cpu().numpy(), x)
+    assert np.allclose(r.h.cpu().numpy(), h, rtol=1e-12, atol=0)
+    assert (h < 1e-20).all()
+    # the same cells under the persistent queue
+    S.set_opts(chem.default_opts(rtol=1e-300, atol=1e-300, schedule=chem.PERSISTENT))
+    rp = _run(S, _to(x), wl.dt)
+    assert _eq(r, rp)
 
 
 def test_kernel_timing_and_workspace_info(tiny, spray):

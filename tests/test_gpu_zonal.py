@@ -361,9 +361,9 @@ def test_zonal_and_chained_steps_captured_by_the_caller(tmp_path):
 
 
 def test_zone_config_errors(tmp_path):
-    mech, path, _ = _states("tiny9", 4, str(tmp_path))
+    mech, path, phi = _states("tiny9", 4, str(tmp_path))
     S = chem.Solver(chem.Mechanism(path), chem.default_opts())
-    x = torch.zeros((4, mech.n_species + 2), dtype=torch.float64, device=DEV)
+    x = torch.from_numpy(phi).to(DEV)
     with pytest.raises(chem.ChemError) as e:
         S.integrate_zonal(x, 1e-6)
     assert e.value.code == -5
@@ -380,7 +380,13 @@ def test_zone_config_errors(tmp_path):
     with pytest.raises(chem.ChemError):
         S.zone_config(c, yf, yo, float("nan"), T_TOL)
     # bands: a negative width, and more than 64 bands for z_max
-    with pytest.raises(chem.ChemError):
-        S.zone_config(c, yf, yo, 0.3, T_TOL, dz=-0.01)
-    with pytest.raises(chem.ChemError):
-        S.zone_config(c, yf, yo, 0.3, T_TOL, dz=0.001)
+    # a rejected band width leaves no zone behind either, even though the
+    # zone itself was configured before the width was checked
+    for bad_dz in (-0.01, 0.001, float("inf")):
+        S.zone_config(c, yf, yo, Z_MAX, T_TOL)
+        S.integrate_zonal(x, 1e-6)
+        with pytest.raises(chem.ChemError):
+            S.zone_config(c, yf, yo, 0.3, T_TOL, dz=bad_dz)
+        with pytest.raises(chem.ChemError) as e:
+            S.integrate_zonal(x, 1e-6)
+        assert e.value.code == -5, bad_dz

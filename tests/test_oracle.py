@@ -223,6 +223,95 @@ def test_troe_reduces_to_lindemann(mech_dir):
         assert abs(q[0] - expect) <= 1e-14 * abs(expect)
 
 
+def _conc(mech, T, p, Y):
+    Wbar = 1.0 / np.sum(Y / mech.W)
+    rho = p * Wbar / (R_GAS * T)
+    return rho * Y / mech.W
+
+
+def test_third_body_nonunit_efficiencies(mech_dir):
+    """Efficiency 0 for species 2 and 3 for species 3 (all others 1): the
+    third-body concentration is p/(RT) - C_2 + 2 C_3, so a wrong species index
+    in the efficiency lookup, or an efficiency applied as alpha - 1 twice,
+    moves q off the closed form."""
+    mech = mechs.third_body_efficiencies(A=1.0e2)
+    M = O.Mech(_write(mech, mech_dir, "tbeff"))
+    for T, p, Y in [(1500.0, 3.0e5, [0.2, 0.3, 0.1, 0.4]), (900.0, 6.0e6, [0.05, 0.15, 0.5, 0.3]),
+                    (2400.0, 1.0e4, [0.4, 0.1, 0.3, 0.2])]:
+        Y = np.array(Y)
+        C = _conc(mech, T, p, Y)
+        Mconc = p / (R_GAS * T) - C[2] + 2.0 * C[3]
+        _, kr, q = M.rates(T, p, Y)
+        expect = 1.0e2 * Mconc * C[0] * C[1]
+        assert kr[0] == 0.0
+        assert abs(q[0] - expect) <= 1e-14 * abs(expect), (T, p)
+
+
+def _troe_fcent(a, T3, T1, T2, T):
+    return (1.0 - a) * math.exp(-T / T3) + a * math.exp(-T / T1) + math.exp(-T2 / T)
+
+
+@pytest.mark.parametrize("T", [650.0, 1100.0, 1800.0, 2600.0])
+def test_troe_broadening_closed_form_points(T, mech_dir):
+    """Troe falloff with a, T3, T1 and T2 all active (Fcent away from 1),
+    both rate constants with b != 0 and Ea != 0, and efficiencies 0 and 3.
+
+    With L = log10 Fcent, c = -0.4 - 0.67 L, N = 0.75 - 1.27 L, d = 0.14 and
+    X = log10 Pr + c, the broadening is log10 F = L / (1 + (X/(N - dX))^2).
+    Two pressures are chosen for each T so that it takes closed values:
+    X = 0 gives F = Fcent exactly (pins c and the T2 term), and
+    X = N/(1+d) gives X/(N - dX) = 1, so F = Fcent^(1/2) (pins N and d).
+    The rate of progress is then q = k_inf Pr/(1+Pr) F C_A C_B."""
+    kw = dict(A=3.0e6, b=0.7, Ea=2.2e4, A0=5.0e3, b0=-1.3, Ea0=9.0e3, a=0.62, T3=170.0, T1=1900.0,
+              T2=4300.0)
+    mech = mechs.troe_general(**kw)
+    M = O.Mech(_write(mech, mech_dir, "troegen_%d" % int(T)))
+    Y = np.array([0.3, 0.25, 0.15, 0.3])
+    Fc = _troe_fcent(kw["a"], kw["T3"], kw["T1"], kw["T2"], T)
+    assert abs(Fc - 1.0) > 0.05          # away from the Lindemann limit
+    L = math.log10(Fc)
+    c, N, d = -0.4 - 0.67 * L, 0.75 - 1.27 * L, 0.14
+    kinf = kw["A"] * T ** kw["b"] * math.exp(-kw["Ea"] / (R_GAS * T))
+    k0 = kw["A0"] * T ** kw["b0"] * math.exp(-kw["Ea0"] / (R_GAS * T))
+    # [M] = (p/(RT)) (1 - X_2 + 2 X_3) with mole fractions X, so Pr is linear in p
+    X_mole = (Y / mech.W) / np.sum(Y / mech.W)
+    m_per_ctot = 1.0 - X_mole[2] + 2.0 * X_mole[3]
+    for logPr, F_exp in [(0.4 + 0.67 * L, Fc), (N / (1.0 + d) - c, math.sqrt(Fc))]:
+        Pr = 10.0 ** logPr
+        p = Pr * kinf / k0 / m_per_ctot * R_GAS * T
+        C = _conc(mech, T, p, Y)
+        expect = kinf * Pr / (1.0 + Pr) * F_exp * C[0] * C[1]
+        kf, kr, q = M.rates(T, p, Y)
+        assert abs(kf[0] - kinf) <= 1e-14 * kinf
+        assert kr[0] == 0.0
+        assert abs(q[0] - expect) <= 1e-12 * abs(expect), (T, logPr, q[0] / expect - 1.0)
+
+
+def test_arrhenius_temperature_dependence_recovered(mech_dir):
+    """kf = A T^b exp(-Ea/(RT)) with b != 0 and Ea != 0: ln kf at three
+    temperatures determines (ln A, b, Ea/R) through an exact 3x3 solve of
+    ln kf = ln A + b ln T - (Ea/R)/T. A units slip in Ea or R, or a wrong sign
+    of b, moves the recovered triple off the file's values. For the isomer
+    pair Kc = exp(a7_B - a7_A) does not depend on T, so ln kr recovers the
+    same b and Ea/R with ln A lowered by the a7 shift."""
+    A, b, Ea, shift = 4.0e9, 1.7, 8.5e4, 0.45
+    mech = mechs.arrhenius_isomer(A, b, Ea, shift)
+    M = O.Mech(_write(mech, mech_dir, "arr"))
+    expect = np.array([math.log(A), b, Ea / R_GAS])
+    for Ts in ([700.0, 1300.0, 2400.0], [300.0, 1000.0, 5000.0]):
+        Ts = np.array(Ts)
+        lkf, lkr = [], []
+        for T in Ts:
+            kf, kr, _ = M.rates(T, 1e5, np.array([0.5, 0.5]))
+            lkf.append(math.log(kf[0]))
+            lkr.append(math.log(kr[0]))
+        G = np.stack([np.ones(3), np.log(Ts), -1.0 / Ts], axis=1)
+        xf = np.linalg.solve(G, np.array(lkf))
+        xr = np.linalg.solve(G, np.array(lkr))
+        assert np.all(np.abs(xf - expect) <= 1e-12 * np.abs(expect)), xf - expect
+        assert np.all(np.abs(xr - (expect - [shift, 0.0, 0.0])) <= 1e-12 * np.abs(expect)), xr - expect
+
+
 def test_thermo_derivatives(mech_dir):
     mech, path = synth.mech_cached("spray54", mech_dir)
     M = O.Mech(path)
