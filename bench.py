@@ -286,6 +286,21 @@ def main():
                      "cells_per_wave": o.cells_per_wave, "sample_cells": len(idx)}
         log("autotuned on %d cells: %s" % (len(idx), tuned))
 
+    # plain gets its own best launch shape (waves per block, cells per wave),
+    # picked by the autotuner on a seeded sample, so that the schedules are
+    # compared at their best shapes rather than at a shape chosen for another
+    plain_shape = None
+    if "plain" in scheds:
+        idx = synth.sample_indices(n_cells, min(16384, n_cells), 13)
+        sample = torch.from_numpy(np.ascontiguousarray(phi[idx])).to("cuda:0")
+        S.set_opts(chem.default_opts(schedule=chem.PLAIN, **TOL))
+        S.autotune(sample, wl.dt)
+        o = S.opts
+        plain_shape = {"waves_per_block": o.waves_per_block, "cells_per_wave": o.cells_per_wave,
+                       "tuned_on_cells": len(idx)}
+        log("plain launch shape autotuned on %d cells: %s" % (len(idx), plain_shape))
+        del sample
+
     codes = {"plain": chem.PLAIN, "persistent": chem.PERSISTENT, "binned": chem.PERSISTENT_BINNED,
              "truebins": chem.PERSISTENT_BINNED, "zonal": chem.PERSISTENT}
     if "zonal" in scheds:
@@ -306,6 +321,9 @@ def main():
                 "cuda:0")
             S.set_cost_override(true_cost)
         extra = {}
+        if sched == "plain" and plain_shape:
+            extra = {"waves_per_block": plain_shape["waves_per_block"],
+                     "cells_per_wave": plain_shape["cells_per_wave"]}
         if tuned and sched != "plain":
             extra = {"waves_per_block": tuned["waves_per_block"], "queue_chunk": tuned["queue_chunk"],
                      "cells_per_wave": tuned["cells_per_wave"]}
@@ -402,6 +420,8 @@ def main():
                                      "frac": fp64["frac"], "flops_per_launch": flops}}
     if "plain" in results and head != "plain":
         line["speedup_vs_plain"] = R["cells_per_s"] / results["plain"]["cells_per_s"]
+    if plain_shape is not None:
+        line["plain_shape"] = plain_shape
     if "zonal" in results:
         Zr = results["zonal"]
         zl = {"z_max": z_max, "t_tol_K": t_tol, "band_width": dz, "mapped_frac": float(Zr["mapped"].mean())}

@@ -141,13 +141,13 @@ struct Grp {
 };
 
 // Per-cell LDS area layout (doubles): J [NN*NN] row-major, pivot-row buffer
-// P [NN+1 rounded to even], a reaction/species buffer RB [max(5*nr, 3*NN)],
-// then the per-species vectors C, gRT, hRT [NN-1 each; entries from ns on
-// are zero, so column loops run to NN-1 without a bound check]. RB holds,
-// for state sizes up to 32, the per-reaction rate of progress (and with the
-// Jacobian kf*theta, kr*theta, q0*dtheta/d[M], dq/dT) read by the species
-// pass; above 32 it holds the species sums omega, d omega/dT and
-// sum nu q0 dtheta/d[M] [NN each] that the reaction lanes add into.
+// P [NN+1 rounded to even], a reaction/species buffer RB, then the
+// per-species vectors C, gRT, hRT [NN-1 each; entries from ns on are zero,
+// so column loops run to NN-1 without a bound check]. RB holds, for state
+// sizes up to 32, the per-reaction rate of progress (and with the Jacobian
+// kf*theta, kr*theta, q0*dtheta/d[M], dq/dT) read by the species pass
+// [max(5*nr, 3*NN)]; above 32 only the species sums omega, d omega/dT and
+// sum nu q0 dtheta/d[M] [3*NN] that the reaction lanes add into.
 struct CellArea {
   double* J;
   double* P;
@@ -158,7 +158,11 @@ struct CellArea {
 };
 
 __host__ __device__ constexpr int pbuf_doubles(int nn) { return (nn + 2) & ~1; }
-__host__ __device__ constexpr int rbuf_doubles(int nn, int nr) { return 5 * nr > 3 * nn ? 5 * nr : 3 * nn; }
+// state sizes above 32 assemble rates and Jacobian reaction by reaction
+__host__ __device__ constexpr bool reaction_major(int nn) { return nn > 32; }
+__host__ __device__ constexpr int rbuf_doubles(int nn, int nr) {
+  return reaction_major(nn) ? 3 * nn : (5 * nr > 3 * nn ? 5 * nr : 3 * nn);
+}
 __host__ __device__ constexpr int cell_doubles_c(int nn, int nr, int ns) {
   return ((nn * nn + 1) & ~1) + pbuf_doubles(nn) + rbuf_doubles(nn, nr) + 3 * (nn - 1);
 }
@@ -269,7 +273,7 @@ struct Cell {
   // state sizes above 32 (only 64-lane groups exist there); smaller sizes,
   // which also run several cells per wave, keep the species-major passes,
   // whose order of additions does not depend on the group width.
-  static constexpr bool kScatter = NN > 32;
+  static constexpr bool kScatter = reaction_major(NN);
 
   // f = dy/dt at y (this lane's component); with JAC also the analytical
   // Jacobian df/dy, written row-major into ca.J (complete on return).

@@ -8,6 +8,14 @@ parity tests), plain and persistent schedules bit-identical.
   25 species -> n = 26, per-wave kernel of size 32 (species-major passes)
   40 species -> n = 41, per-wave kernel of size 55 (reaction-major passes)
  100 species -> n = 101, workgroup kernel, ld = 112
+ 143 species -> n = 144, workgroup kernel, ld = 144: the LU's last panel is
+                a full 12 columns and no leading-dimension padding is left
+ 144 species -> n = 145, workgroup kernel, ld = 160: the LU's last panel has
+                a single column (its index arithmetic is checked in bounds on
+                the CPU by tests/test_wide_lu_bounds.py for every n)
+
+At most one cell (0.1% rounded up) may take another step sequence than the
+oracle's.
 """
 import os
 
@@ -41,7 +49,8 @@ def _run(S, x, dt):
     return [t.cpu().numpy() for t in (r.phi, h, r.n_acc, r.n_rej, r.status)]
 
 
-@pytest.mark.parametrize("ns,nr,n3,nt", [(25, 90, 10, 3), (40, 160, 20, 6), (100, 450, 60, 15)])
+@pytest.mark.parametrize("ns,nr,n3,nt", [(25, 90, 10, 3), (40, 160, 20, 6), (100, 450, 60, 15),
+                                         (143, 600, 80, 20), (144, 600, 80, 20)])
 def test_padded_state_sizes(tmp_path, ns, nr, n3, nt):
     mech = synth.generate_mechanism(ns, nr, n3, nt, 1000 + ns, ea_by_class=True)
     path = synth.write_mech(mech, str(tmp_path / ("m%d.mech" % ns)))
@@ -71,7 +80,7 @@ def test_padded_state_sizes(tmp_path, ns, nr, n3, nt):
     gphi, _, gna, gnr, gst = plain
     assert np.array_equal(gst, st)
     same = (gna == na) & (gnr == nr_)
-    assert (~same).sum() <= 2, "%d of %d cells took another step sequence" % ((~same).sum(), len(same))
+    assert (~same).sum() <= 1, "%d of %d cells took another step sequence" % ((~same).sum(), len(same))
     dT = np.abs(gphi[:, 0] - ref[:, 0])
     dY = np.abs(gphi[:, 2:] - ref[:, 2:])
     tolY = 1e-10 + 1e-6 * np.abs(ref[:, 2:])
@@ -81,4 +90,4 @@ def test_padded_state_sizes(tmp_path, ns, nr, n3, nt):
     assert np.all(dY[~same] <= 10 * tolY[~same])
     assert np.array_equal(gphi[:, 1], phi[:, 1])
     print("ns=%d: %d/%d cells on the oracle's step sequence, substeps %d..%d" %
-          (ns, same.sum(), len(same), (na + nr_).min(), (na + nr_).max()))
+          (ns, same.sum(), len(same), (na + nr_).min(), (na + nr_).max()), flush=True)

@@ -1,0 +1,91 @@
+"""Bounds of the large-mechanism LU's index arithmetic, checked on the CPU.
+
+`tests/wide_lu_bounds.c` replays the workgroup kernel's blocked LU and
+triangular solves (their loops, bounds and guards, thread by thread) with
+every LDS and HBM buffer allocated on its own at exactly the kernel's size,
+built with AddressSanitizer. It is run for every state size of the workgroup
+kernel (65..256), so every tail panel width appears, including 1 (n = 1 mod
+12) and a full last panel (n = 0 mod 12). Two layouts are covered: the
+shipped one (12-column panels, U block in LDS) and a 16-column panel whose
+trailing update reads the U block from the matrix in HBM. The matrices
+include pivots taken from the last row at every step and a singular last
+column. The replica's factors and pivots must equal the oracle's in every
+bit, which shows that it follows the kernel's arithmetic; its solutions must
+match the oracle's to rounding.
+"""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "wide_lu_bounds.c")
+
+
+@pytest.fixture(scope="module")
+def exe(tmp_path_factory):
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    d = tmp_path_factory.mktemp("wlb")
+    out = str(d / "wide_lu_bounds")
+    san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+    subprocess.check_call(["gcc", "-std=gnu11", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off"] + san
+                          + ["-o", out, SRC, "-lm"])
+    return out, str(d)
+
+
+def _read(path):
+    raw = open(path, "rb").read()
+    off, out = 0, []
+    while off < len(raw):
+        n, ld, info = np.frombuffer(raw, dtype=np.int32, count=3, offset=off)
+        off += 12
+        A = np.frombuffer(raw, dtype=np.float64, count=n * n, offset=off).reshape(n, n)
+        off += 8 * n * n
+        F = np.frombuffer(raw, dtype=np.float64, count=n * n, offset=off).reshape(n, n)
+        off += 8 * n * n
+        piv = np.frombuffer(raw, dtype=np.int32, count=n, offset=off)
+        off += 4 * n
+        x = np.frombuffer(raw, dtype=np.float64, count=n, offset=off)
+        off += 8 * n
+        out.append((int(n), int(ld), int(info), A, F, piv, x))
+    return out
+
+
+# the shipped layout at every size of the workgroup kernel; the other layouts
+# and matrix patterns on a window of sizes that holds every tail width twice
+CASES = [(12, 0, 0, 65, 256)] + [
+    (panel, u_hbm, pattern, 140, 140 + 2 * panel - 1)
+    for panel, u_hbm in [(12, 0), (16, 1), (16, 0), (12, 1)] for pattern in (0, 1, 3)
+    if (panel, u_hbm, pattern) != (12, 0, 0)] + [(16, 1, 0, 224, 256), (12, 0, 1, 225, 256)]
+
+
+@pytest.mark.parametrize("panel,u_hbm,pattern,n_lo,n_hi", CASES)
+def test_wide_lu_in_bounds(exe, panel, u_hbm, pattern, n_lo, n_hi):
+    path, d = exe
+    out = os.path.join(d, "r_%d_%d_%d_%d.bin" % (panel, u_hbm, pattern, n_lo))
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:exitcode=23")
+    r = subprocess.run([path, out, str(panel), str(u_hbm), str(n_lo), str(n_hi), str(pattern)], env=env,
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    res = _read(out)
+    assert [n for n, *_ in res] == list(range(n_lo, n_hi + 1))
+    tails = set()
+    for n, ld, info, A, F, piv, x in res:
+        tails.add((n - 1) % panel + 1)
+        LU, piv_o, info_o = O.lu(A)
+        assert info == info_o, n
+        assert np.array_equal(piv, piv_o), n
+        assert np.array_equal(F, LU), n          # same operations in the same order
+        if pattern == 1:
+            assert (piv[:-1] == n - 1).all(), n
+        if info == 0:
+            xo = O.lu_solve(LU, piv_o, np.arange(n, dtype=float) + 1)
+            assert np.max(np.abs(x - xo)) <= 1e-12 * np.max(np.abs(xo)), n
+        else:
+            assert pattern == 3 and info == n
+    assert tails == set(range(1, panel + 1))   # every tail panel width, 1 and full included
