@@ -548,23 +548,58 @@ void orc_lu_solve(int n, const double* LU, const int* piv, double* b) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Rodas3 (transformed form: unknowns u_i, matrix M = I/(gamma h) - J)       */
+/* Rosenbrock methods in the transformed form: unknowns u_i, matrix          */
+/* M = I/(gamma h) - J, stage i solves                                       */
+/*   M u_i = f(y + sum_j a_ij u_j) + sum_j (c_ij / h) u_j,                   */
+/* y_new = y + sum_j m_j u_j, error estimate sum_j e_j u_j.                  */
 /* ------------------------------------------------------------------------ */
 
-static const double RO_GAMMA = 0.5;
-/* a[i][j], c[i][j] strictly lower, i = stage */
-static const double RO_A[4][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {2, 0, 0, 0}, {2, 0, 1, 0}};
-static const double RO_C[4][4] = {{0, 0, 0, 0}, {4, 0, 0, 0}, {1, -1, 0, 0}, {1, -1, -8.0 / 3.0, 0}};
-static const double RO_M[4] = {2, 0, 1, 1};
-static const double RO_E[4] = {0, 0, 0, 1};
+typedef struct {
+  int stages;
+  double gamma;
+  double a[4][4], c[4][4]; /* strictly lower, row = stage */
+  double m[4], e[4];
+} tableau_t;
+
+/* Rodas3 (Sandu et al. 1997): order 3, embedded order 2, L-stable, stiffly
+ * accurate. Stage 2 has a zero a-row and reuses f(y). */
+static const tableau_t RODAS3 = {
+    4, 0.5,
+    {{0, 0, 0, 0}, {0, 0, 0, 0}, {2, 0, 0, 0}, {2, 0, 1, 0}},
+    {{0, 0, 0, 0}, {4, 0, 0, 0}, {1, -1, 0, 0}, {1, -1, -8.0 / 3.0, 0}},
+    {2, 0, 1, 1},
+    {0, 0, 0, 1}};
+
+/* ROS4 of Shampine (1982), the first coefficient set of Hairer and Wanner's
+ * Rosenbrock code family: order 4, embedded order 3, gamma = 1/2. Stage 4
+ * has the a-row of stage 3 and so the same argument of f. */
+static const tableau_t ROS4 = {
+    4, 0.5,
+    {{0, 0, 0, 0}, {2, 0, 0, 0}, {48.0 / 25.0, 6.0 / 25.0, 0, 0}, {48.0 / 25.0, 6.0 / 25.0, 0, 0}},
+    {{0, 0, 0, 0}, {-8, 0, 0, 0}, {372.0 / 25.0, 12.0 / 5.0, 0, 0}, {-112.0 / 125.0, -54.0 / 125.0, -2.0 / 5.0, 0}},
+    {19.0 / 9.0, 1.0 / 2.0, 25.0 / 108.0, 125.0 / 108.0},
+    {17.0 / 54.0, 7.0 / 36.0, 0, 125.0 / 108.0}};
+
+static const tableau_t* tableau_of(int scheme) {
+  if (scheme == ORC_RODAS3) return &RODAS3;
+  if (scheme == ORC_ROS4) return &ROS4;
+  return NULL;
+}
+
+int orc_tableau(int scheme, double* gamma, double* a, double* c, double* mw, double* e) {
+  const tableau_t* tb = tableau_of(scheme);
+  if (!tb) return -1;
+  *gamma = tb->gamma;
+  for (int i = 0; i < 4; ++i) {
+    for (int j = 0; j < 4; ++j) { a[4 * i + j] = tb->a[i][j]; c[4 * i + j] = tb->c[i][j]; }
+    mw[i] = tb->m[i];
+    e[i] = tb->e[i];
+  }
+  return tb->stages;
+}
 
 void orc_rodas3_tableau(double* gamma, double* a, double* c, double* mw, double* e) {
-  *gamma = RO_GAMMA;
-  for (int i = 0; i < 4; ++i) {
-    for (int j = 0; j < 4; ++j) { a[4 * i + j] = RO_A[i][j]; c[4 * i + j] = RO_C[i][j]; }
-    mw[i] = RO_M[i];
-    e[i] = RO_E[i];
-  }
+  orc_tableau(ORC_RODAS3, gamma, a, c, mw, e);
 }
 
 typedef struct {
@@ -588,33 +623,45 @@ static void work_free(work_t* w) {
   free(w->f0); free(w->J); free(w->M); free(w->u); free(w->ys); free(w->fs); free(w->rhs); free(w->piv);
 }
 
+/* Where stage s takes its f from: 0 = f(y) (its a-row is zero), 1 = the f of
+ * stage s-1 (its a-row equals stage s-1's, so the argument is the same), 2 =
+ * a new evaluation at y + sum_j a_sj u_j. */
+static int stage_f_source(const tableau_t* tb, int s) {
+  int zero = 1, same = s > 0;
+  for (int j = 0; j < 4; ++j) {
+    if (j < s && tb->a[s][j] != 0.0) zero = 0;
+    if (s > 0 && tb->a[s][j] != tb->a[s - 1][j]) same = 0;
+  }
+  if (zero) return 0;
+  if (same && stage_f_source(tb, s - 1) == 2) return 1;
+  return 2;
+}
+
 /* One attempted step of size h from y, with f0 = f(y) and J = J(y) given.
- * Stage i: u_i = M^-1 ( f(y + sum_j a_ij u_j) + sum_j (c_ij / h) u_j ); a stage
- * whose a-row is zero reuses f0. Returns the LU status. */
-static int rodas3_attempt(const orc_mech* m, double p, const double* y, double h, work_t* w,
-                          double* y_new, double* err_vec) {
+ * Returns the LU status. */
+static int ros_attempt(const orc_mech* m, const tableau_t* tb, double p, const double* y, double h, work_t* w,
+                       double* y_new, double* err_vec) {
   int n = w->n;
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j)
-      w->M[(size_t)i * n + j] = (i == j ? 1.0 / (RO_GAMMA * h) : 0.0) - w->J[(size_t)i * n + j];
+      w->M[(size_t)i * n + j] = (i == j ? 1.0 / (tb->gamma * h) : 0.0) - w->J[(size_t)i * n + j];
   int info = orc_lu(n, w->M, w->piv);
   if (info) return info;
-  for (int s = 0; s < 4; ++s) {
-    int newf = 0;
-    for (int j = 0; j < s; ++j) if (RO_A[s][j] != 0.0) newf = 1;
-    if (newf) {
+  for (int s = 0; s < tb->stages; ++s) {
+    int src = stage_f_source(tb, s);
+    if (src == 2) {
       for (int i = 0; i < n; ++i) {
         double v = y[i];
-        for (int j = 0; j < s; ++j) v = v + RO_A[s][j] * w->u[j * n + i];
+        for (int j = 0; j < s; ++j) v = v + tb->a[s][j] * w->u[j * n + i];
         w->ys[i] = v;
       }
       orc_rhs(m, p, w->ys, w->fs);
-    } else {
+    } else if (src == 0) {
       for (int i = 0; i < n; ++i) w->fs[i] = w->f0[i];
-    }
+    } /* src == 1: fs still holds stage s-1's f */
     for (int i = 0; i < n; ++i) {
       double v = w->fs[i];
-      for (int j = 0; j < s; ++j) v = v + (RO_C[s][j] / h) * w->u[j * n + i];
+      for (int j = 0; j < s; ++j) v = v + (tb->c[s][j] / h) * w->u[j * n + i];
       w->rhs[i] = v;
     }
     orc_lu_solve(n, w->M, w->piv, w->rhs);
@@ -622,22 +669,32 @@ static int rodas3_attempt(const orc_mech* m, double p, const double* y, double h
   }
   for (int i = 0; i < n; ++i) {
     double v = y[i], e = 0.0;
-    for (int j = 0; j < 4; ++j) { v = v + RO_M[j] * w->u[j * n + i]; e = e + RO_E[j] * w->u[j * n + i]; }
+    for (int j = 0; j < tb->stages; ++j) {
+      v = v + tb->m[j] * w->u[j * n + i];
+      e = e + tb->e[j] * w->u[j * n + i];
+    }
     y_new[i] = v;
     err_vec[i] = e;
   }
   return 0;
 }
 
-int orc_rodas3_step(const orc_mech* m, double p, const double* y, double h, double* y_new,
-                    double* err_vec) {
+int orc_step(const orc_mech* m, int scheme, double p, const double* y, double h, double* y_new,
+             double* err_vec) {
+  const tableau_t* tb = tableau_of(scheme);
+  if (!tb) return -1;
   work_t w;
   work_alloc(&w, m->ns + 1);
   orc_rhs(m, p, y, w.f0);
   orc_jac(m, p, y, w.J);
-  int info = rodas3_attempt(m, p, y, h, &w, y_new, err_vec);
+  int info = ros_attempt(m, tb, p, y, h, &w, y_new, err_vec);
   work_free(&w);
   return info;
+}
+
+int orc_rodas3_step(const orc_mech* m, double p, const double* y, double h, double* y_new,
+                    double* err_vec) {
+  return orc_step(m, ORC_RODAS3, p, y, h, y_new, err_vec);
 }
 
 /* Step-size controller constants (fixed; the GPU library uses the same). */
@@ -654,6 +711,7 @@ static int integrate_cell(const orc_mech* m, double p, double dt, const orc_opts
                           double* h_io, int* nacc_out, int* nrej_out, work_t* w, double* y_new,
                           double* err_vec) {
   int n = m->ns + 1;
+  const tableau_t* tb = tableau_of(o->scheme);
   int nacc = 0, nrej = 0, attempts = 0, status = ORC_OK;
   for (int i = 0; i < n; ++i) if (!isfinite(y[i])) status = ORC_NONFINITE;
   if (!isfinite(p) || !(p > 0.0)) status = ORC_NONFINITE;
@@ -673,7 +731,7 @@ static int integrate_cell(const orc_mech* m, double p, double dt, const orc_opts
     int clipped = 0;
     if (hc >= rem) { hc = rem; clipped = 1; }
     if (hc < H_MIN) { status = ORC_H_UNDERFLOW; break; }
-    int info = rodas3_attempt(m, p, y, hc, w, y_new, err_vec);
+    int info = ros_attempt(m, tb, p, y, hc, w, y_new, err_vec);
     attempts++;
     if (info) { status = ORC_SINGULAR; break; }
     /* RMS error over all components */
@@ -767,7 +825,7 @@ static void* worker(void* arg) {
 int orc_integrate(const orc_mech* m, long n_cells, double dt, const orc_opts* o,
                   const double* phi_in, double* phi_out, double* h_io, int* n_acc, int* n_rej,
                   signed char* status, int n_threads) {
-  if (!m || !o || n_cells < 0 || !(dt > 0.0) || (n_cells > 0 && (!phi_in || !phi_out))) {
+  if (!m || !o || n_cells < 0 || !(dt > 0.0) || (n_cells > 0 && (!phi_in || !phi_out)) || !tableau_of(o->scheme)) {
     snprintf(g_err, sizeof g_err, "orc_integrate: bad argument");
     return -1;
   }

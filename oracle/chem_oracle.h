@@ -37,7 +37,11 @@ typedef struct {
   double rtol;      /* relative tolerance */
   double atol;      /* absolute tolerance, same for T and every Y */
   int max_steps;    /* attempted steps per cell per call */
+  int scheme;       /* ORC_RODAS3 (0) or ORC_ROS4 (1) */
 } orc_opts;
+
+/* Rosenbrock schemes (the paper leaves the scheme unnamed). */
+enum { ORC_RODAS3 = 0, ORC_ROS4 = 1 };
 
 /* Per-cell status codes. */
 enum { ORC_OK = 0, ORC_MAX_STEPS = 1, ORC_H_UNDERFLOW = 2, ORC_NONFINITE = 3,
@@ -71,11 +75,15 @@ int orc_lu(int n, double* A, int* piv);
 /* Solve with the factors of orc_lu; b is overwritten with x. */
 void orc_lu_solve(int n, const double* LU, const int* piv, double* b);
 
-/* Rodas3 coefficients: gamma, strictly lower a[4][4] and c[4][4] (row-major),
- * solution weights m[4], error weights e[4]. */
+/* Coefficients of a scheme in the transformed form: gamma, strictly lower
+ * a[4][4] and c[4][4] (row-major, row = stage), solution weights m[4], error
+ * weights e[4]. Returns the number of stages, or -1 for an unknown scheme. */
+int orc_tableau(int scheme, double* gamma, double* a, double* c, double* m, double* e);
 void orc_rodas3_tableau(double* gamma, double* a, double* c, double* m, double* e);
-/* One Rodas3 step of size h from y: y_new and the embedded error vector.
- * Returns the LU status (0 or k+1). */
+/* One step of size h from y: y_new and the embedded error vector. Returns
+ * the LU status (0 or k+1), or -1 for an unknown scheme. */
+int orc_step(const orc_mech* m, int scheme, double p, const double* y, double h, double* y_new,
+             double* err_vec);
 int orc_rodas3_step(const orc_mech* m, double p, const double* y, double h, double* y_new,
                     double* err_vec);
 

@@ -34,7 +34,11 @@ def build(verbose: bool = False) -> str:
 
 
 class _Opts(ctypes.Structure):
-    _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("max_steps", ctypes.c_int)]
+    _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("max_steps", ctypes.c_int),
+                ("scheme", ctypes.c_int)]
+
+
+RODAS3, ROS4 = 0, 1
 
 
 _lib = None
@@ -59,6 +63,8 @@ def lib():
         L.orc_lu_solve.argtypes = [ctypes.c_int, _dp, _ip, _dp]
         L.orc_rodas3_tableau.argtypes = [_dp, _dp, _dp, _dp, _dp]
         L.orc_rodas3_step.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, ctypes.c_double, _dp, _dp]
+        L.orc_tableau.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _dp, ctypes.c_double, _dp, _dp]
         L.orc_integrate.argtypes = [ctypes.c_void_p, ctypes.c_long, ctypes.c_double,
                                     ctypes.POINTER(_Opts), _dp, _dp, _dp, _ip, _ip,
                                     ctypes.POINTER(ctypes.c_byte), ctypes.c_int]
@@ -133,8 +139,19 @@ class Mech:
             raise FloatingPointError("singular matrix at column %d" % (info - 1))
         return yn, e
 
+    def step(self, p: float, y, h: float, scheme: int = RODAS3):
+        """One step of the given scheme from y with step h: (y_new, error vector)."""
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        yn, e = np.zeros(self.n), np.zeros(self.n)
+        info = lib().orc_step(self._h, int(scheme), float(p), _d(y), float(h), _d(yn), _d(e))
+        if info < 0:
+            raise ValueError("unknown scheme %d" % scheme)
+        if info:
+            raise FloatingPointError("singular matrix at column %d" % (info - 1))
+        return yn, e
+
     def integrate(self, phi, dt: float, rtol=1e-6, atol=1e-10, max_steps=100000, h_io=None,
-                  n_threads: int = 1):
+                  n_threads: int = 1, scheme: int = RODAS3):
         phi = np.ascontiguousarray(phi, dtype=np.float64)
         n_cells = phi.shape[0]
         assert phi.shape[1] == self.ns + 2
@@ -143,7 +160,7 @@ class Mech:
         na = np.zeros(n_cells, dtype=np.int32)
         nr = np.zeros(n_cells, dtype=np.int32)
         st = np.zeros(n_cells, dtype=np.int8)
-        o = _Opts(rtol, atol, max_steps)
+        o = _Opts(rtol, atol, max_steps, scheme)
         rc = lib().orc_integrate(self._h, n_cells, float(dt), ctypes.byref(o), _d(phi), _d(out), _d(h),
                                  _i(na), _i(nr), st.ctypes.data_as(ctypes.POINTER(ctypes.c_byte)),
                                  int(n_threads))
@@ -238,6 +255,17 @@ def lu_solve(LU, piv, b):
     lib().orc_lu_solve(LU.shape[0], _d(np.ascontiguousarray(LU)), _i(np.ascontiguousarray(piv, dtype=np.int32)),
                        _d(b))
     return b
+
+
+def tableau(scheme: int):
+    """(stages, gamma, a [4,4], c [4,4], m [4], e [4]) of a scheme."""
+    g = np.zeros(1)
+    a, c = np.zeros(16), np.zeros(16)
+    m, e = np.zeros(4), np.zeros(4)
+    st = lib().orc_tableau(int(scheme), _d(g), _d(a), _d(c), _d(m), _d(e))
+    if st < 0:
+        raise ValueError("unknown scheme %d" % scheme)
+    return st, g[0], a.reshape(4, 4), c.reshape(4, 4), m, e
 
 
 def rodas3_tableau():

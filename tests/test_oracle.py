@@ -571,3 +571,167 @@ def test_status_codes(mech_dir):
     assert (st == 2).all()
     assert (na == 0).all()
     assert np.array_equal(out, phi[2:])
+
+
+# ------------------------------------------------------- ROS4 (NEXT-4) ---
+# The second scheme is a table swap: Shampine's ROS4 (order 4, embedded
+# order 3, gamma = 1/2) in the same transformed form. Its pins are exact
+# (rational) properties of the tableau and closed-form solutions.
+
+def _tab_fractions(scheme):
+    st, g, a, c, m, e = O.tableau(scheme)
+    F = lambda x: Fraction(x).limit_denominator(1000)
+    vals = [g] + list(a.ravel()) + list(c.ravel()) + list(m) + list(e)
+    for x in vals:
+        assert float(F(x)) == x          # every double is exactly its rational's rounding
+    A = [[F(a[i, j]) for j in range(4)] for i in range(4)]
+    C = [[F(c[i, j]) for j in range(4)] for i in range(4)]
+    return st, F(g), A, C, [F(x) for x in m], [F(x) for x in e]
+
+
+def _order_defects(gam, A, C, w):
+    """Defects of the classical Rosenbrock order conditions up to order 4 for
+    weights w (transformed form: Gamma^-1 = I/gamma - c, alpha = a Gamma,
+    b = w Gamma). Hairer and Wanner, Solving ODEs II, Table IV.7.1."""
+    s = 4
+    G = _inv_lower([[(1 / gam if i == j else 0) - C[i][j] for j in range(s)] for i in range(s)])
+    al = [[sum(A[i][k] * G[k][j] for k in range(s)) for j in range(s)] for i in range(s)]
+    be = [[al[i][j] + G[i][j] for j in range(s)] for i in range(s)]
+    b = [sum(w[k] * G[k][j] for k in range(s)) for j in range(s)]
+    ai = [sum(al[i][j] for j in range(i)) for i in range(s)]
+    bp = [sum(be[i][j] for j in range(i)) for i in range(s)]
+    R = range(s)
+    return {
+        1: [sum(b) - 1],
+        2: [sum(b[i] * bp[i] for i in R) - (Fraction(1, 2) - gam)],
+        3: [sum(b[i] * ai[i] ** 2 for i in R) - Fraction(1, 3),
+            sum(b[i] * be[i][j] * bp[j] for i in R for j in range(i)) - (Fraction(1, 6) - gam + gam ** 2)],
+        4: [sum(b[i] * ai[i] ** 3 for i in R) - Fraction(1, 4),
+            sum(b[i] * ai[i] * al[i][j] * bp[j] for i in R for j in range(i)) - (Fraction(1, 8) - gam / 3),
+            sum(b[i] * be[i][j] * ai[j] ** 2 for i in R for j in range(i)) - (Fraction(1, 12) - gam / 3),
+            sum(b[i] * be[i][j] * be[j][k] * bp[k] for i in R for j in range(i) for k in range(j))
+            - (Fraction(1, 24) - gam / 2 + Fraction(3, 2) * gam ** 2 - gam ** 3)],
+    }
+
+
+def test_ros4_order_conditions_exact():
+    st, gam, A, C, M, E = _tab_fractions(O.ROS4)
+    assert st == 4 and gam == Fraction(1, 2)
+    main = _order_defects(gam, A, C, M)
+    emb = _order_defects(gam, A, C, [M[i] - E[i] for i in range(4)])
+    for p in (1, 2, 3, 4):
+        assert all(d == 0 for d in main[p]), (p, main[p])
+    for p in (1, 2, 3):
+        assert all(d == 0 for d in emb[p]), (p, emb[p])
+    assert any(d != 0 for d in emb[4])           # the estimate is of order 3, not 4
+    # the checker is not vacuous: Rodas3 meets order 3 exactly and misses 4
+    _, g3, A3, C3, M3, _ = _tab_fractions(O.RODAS3)
+    r3 = _order_defects(g3, A3, C3, M3)
+    assert all(d == 0 for p in (1, 2, 3) for d in r3[p]) and any(d != 0 for d in r3[4])
+
+
+def _ros_linear(gam, A, C, M, E, z):
+    K = []
+    for i in range(4):
+        r = z * (1 + sum(A[i][j] * K[j] for j in range(i))) + sum(C[i][j] * K[j] for j in range(i))
+        K.append(r / (1 / gam - z))
+    return 1 + sum(M[j] * K[j] for j in range(4)), sum(E[j] * K[j] for j in range(4))
+
+
+def test_ros4_stability_function():
+    """On y' = lambda y the step multiplies y by R(z): R - e^z = O(z^5) and
+    the embedded R - E - e^z = O(z^4) (halving z divides the defect by 32 and
+    16); R(infinity) = 1/3, so the scheme is A-stable (|R(iy)| <= 1) but, unlike
+    Rodas3, not L-stable."""
+    _, gam, A, C, M, E = _tab_fractions(O.ROS4)
+    for order, f in [(4, lambda z: _ros_linear(gam, A, C, M, E, z)[0]),
+                     (3, lambda z: (lambda R, Er: R - Er)(*_ros_linear(gam, A, C, M, E, z)))]:
+        defects = []
+        for k in range(5, 10):
+            z = Fraction(1, 2 ** k)
+            ez = sum(z ** j / math.factorial(j) for j in range(14))
+            defects.append(abs(f(z) - ez))
+        ratios = [float(defects[i] / defects[i + 1]) for i in range(len(defects) - 1)]
+        for r in ratios[1:]:
+            assert abs(r - 2 ** (order + 1)) / 2 ** (order + 1) < 0.1, (order, ratios)
+    R_inf, _ = _ros_linear(gam, A, C, M, E, Fraction(-10) ** 15)
+    assert abs(float(R_inf) - 1.0 / 3.0) < 1e-12
+    for k in range(1, 400):
+        zz = complex(0.0, k / 4.0)
+        Kc = []
+        for i in range(4):
+            r = zz * (1 + sum(float(A[i][j]) * Kc[j] for j in range(i))) + sum(float(C[i][j]) * Kc[j] for j in range(i))
+            Kc.append(r / (float(1 / gam) - zz))
+        assert abs(1 + sum(float(M[j]) * Kc[j] for j in range(4))) <= 1.0 + 1e-14
+
+
+def test_ros4_one_step_isomer(mech_dir):
+    """One fixed ROS4 step on A <=> B moves the distance from equilibrium by
+    exactly R(z) with z = -(kf + kr) h, and the error estimate is E(z) d0."""
+    kf, shift = 2.0e5, 0.7
+    M = O.Mech(_write(mechs.isomer_pair(kf, shift), mech_dir, "iso_r4"))
+    kr = kf / math.exp(shift)
+    yeq = kr / (kf + kr)
+    _, gam, A, C, Mw, E = _tab_fractions(O.ROS4)
+    for h in [1e-7, 3e-6, 1e-4, 1e-2]:
+        y0 = np.array([1200.0, 0.9, 0.1])
+        yn, err = M.step(1e5, y0, h, O.ROS4)
+        R, Er = _ros_linear(gam, A, C, Mw, E, Fraction(-(kf + kr) * h))
+        d0 = y0[1] - yeq
+        assert yn[0] == y0[0]
+        assert abs((yn[1] - yeq) - float(R) * d0) <= 1e-13 * abs(d0)
+        assert abs(err[1] - float(Er) * d0) <= 1e-13 * abs(d0)
+
+
+def test_ros4_convergence_order_termolecular(mech_dir):
+    """Fixed-step ROS4 on 3A -> 3B (closed form C_A = C_A0 / sqrt(1 + 6 k
+    C_A0^2 t)): the main solution converges as h^4, the embedded one as h^3."""
+    k = 1.0e2
+    mech = mechs.termolecular_isomer(k)
+    M = O.Mech(_write(mech, mech_dir, "ter_r4"))
+    T, p = 1000.0, 1.0e5
+    y0 = np.array([T, 1.0, 0.0])
+    C0 = p / (R_GAS * T)
+    rho = p * mech.W[0] / (R_GAS * T)
+    t_end = 2.0 / (k * C0 * C0)
+    exact = C0 / math.sqrt(1 + 6 * k * C0 * C0 * t_end) * mech.W[0] / rho
+    em, ee = [], []
+    for N in [8, 16, 32, 64, 128]:
+        h = t_end / N
+        y, ye = y0.copy(), y0.copy()
+        for _ in range(N):
+            y, _ = M.step(p, y, h, O.ROS4)
+            yn, e = M.step(p, ye, h, O.ROS4)
+            ye = yn - e
+        em.append(abs(y[1] - exact))
+        ee.append(abs(ye[1] - exact))
+    sm = [math.log2(em[i] / em[i + 1]) for i in range(4)]
+    se = [math.log2(ee[i] / ee[i + 1]) for i in range(4)]
+    assert abs(sm[-1] - 4.0) < 0.15 and abs(sm[-2] - 4.0) < 0.15, sm
+    assert abs(se[-1] - 3.0) < 0.1 and abs(se[-2] - 3.0) < 0.15, se
+
+
+def test_ros4_adaptive_closed_form_and_radau(mech_dir):
+    """Adaptive ROS4 on the isomer pair meets the closed form within ten
+    times the tolerance, and on 9-species cells agrees with Rodas3 within the
+    same bound (two different schemes of the same accuracy target)."""
+    kf, shift = 2.0e5, 0.7
+    M = O.Mech(_write(mechs.isomer_pair(kf, shift), mech_dir, "iso2_r4"))
+    kr = kf / math.exp(shift)
+    yeq = kr / (kf + kr)
+    phi = np.array([[1100.0, 1e5, 0.95, 0.05], [900.0, 1e5, 0.0, 1.0]])
+    for dt in [1e-6, 1e-5, 1e-4]:
+        out, h, na, nr, st = M.integrate(phi, dt, scheme=O.ROS4)
+        assert (st == 0).all()
+        ya = yeq + (phi[:, 2] - yeq) * math.exp(-(kf + kr) * dt)
+        assert np.all(np.abs(out[:, 2] - ya) <= 10 * (1e-10 + 1e-6 * np.abs(ya)))
+    wl, mech, path, phi = synth.workload_inputs("tiny9_1024", mech_dir, n_cells=64)
+    T9 = O.Mech(path)
+    a = T9.integrate(phi, wl.dt, scheme=O.ROS4, n_threads=4)
+    b = T9.integrate(phi, wl.dt, scheme=O.RODAS3, n_threads=4)
+    assert (a[4] == 0).all() and (b[4] == 0).all()
+    tol = 1e-10 + 1e-6 * np.abs(b[0][:, 2:])
+    assert np.all(np.abs(a[0][:, 2:] - b[0][:, 2:]) <= 10 * tol)
+    assert np.all(np.abs(a[0][:, 0] - b[0][:, 0]) <= 10 * 1e-6 * b[0][:, 0])
+    with pytest.raises(ValueError):
+        T9.integrate(phi[:2], wl.dt, scheme=7)
