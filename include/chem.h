@@ -142,6 +142,30 @@ int chem_integrate(chem_solver* s, int64_t n_cells, double dt, const double* phi
                    double* phi_out, double* h_io, int32_t* n_acc, int32_t* n_rej,
                    int8_t* status, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * chemistry step as chem_integrate on the persistent queue in index order
+ * (learned binning is not applied, no cost-model log record and no kernel
+ * timing event is made), that allocates and frees nothing. Its queue head,
+ * and for state sizes above 64 the J and M workspace slots of the
+ * workgroup kernel, live in a static device array of
+ * CHEM_NOALLOC_SCRATCH_BYTES (128 MiB) that every GPU the library runs on
+ * holds until the process ends; its address is looked up once per device
+ * when the first solver on that device is created. The workgroup kernel
+ * gets min(resident workgroups, (128 MiB - 256 B) / (2 n ld 8 B)) slots
+ * (289 for n = 161, against 512 in chem_integrate's default budget); a
+ * state size whose one slot would not fit is rejected with
+ * CHEM_EUNSUPPORTED (none up to n = 256 is). The queue head is reset by a
+ * kernel at the start of every call. All calls on one GPU share that GPU's
+ * array, so two calls that overlap in time on one GPU (on different streams
+ * or from different solvers) race and give wrong results: serialise them.
+ * Arrays, results (bit-identical to chem_integrate under any schedule) and
+ * errors as chem_integrate. */
+#define CHEM_NOALLOC_SCRATCH_BYTES (128ll << 20)
+int chem_integrate_noalloc(chem_solver* s, int64_t n_cells, double dt, const double* phi_in,
+                           double* phi_out, double* h_io, int32_t* n_acc, int32_t* n_rej,
+                           int8_t* status, void* stream);
+
 /* Paper: Results and discussion (chemistry is solved in every CFD iteration;
  * the Spray A run times 100 of them).
  * n_steps chained chemistry steps of the same dt, each feeding the next (h_io

@@ -69,6 +69,7 @@ def lib():
             "chem_solver_get_opts": (i32, [_vp, ctypes.POINTER(Opts)]),
             "chem_integrate": (i32, [_vp, i64, dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "chem_integrate_steps": (i32, [_vp, i32, i64, dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "chem_integrate_noalloc": (i32, [_vp, i64, dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "chem_eval_rhs_jac": (i32, [_vp, i64, _vp, _vp, _vp, _vp]),
             "chem_lu_batch": (i32, [_vp, i64, _vp, _vp, _vp, _vp, _vp]),
             "chem_log_enable": (i32, [_vp, i64]),
@@ -245,6 +246,23 @@ class Solver:
                                     _ptr(phi_out, torch.float64, self.device, n * (self.ns + 2), "out"),
                                     _ptr(h, torch.float64, self.device, n, "h_io"),
                                     _ptr(na), _ptr(nr), _ptr(st), _stream(self.device)))
+        return Result(phi_out, h, na, nr, st)
+
+    def integrate_noalloc(self, phi: torch.Tensor, dt: float, h_io: Optional[torch.Tensor] = None,
+                          out: Optional[torch.Tensor] = None) -> Result:
+        """chem_integrate_noalloc: one chemistry step on the persistent queue
+        whose device scratch is the library's static array (the library
+        allocates nothing; the output tensors are allocated here unless
+        given)."""
+        n = phi.shape[0]
+        if phi.dim() != 2 or phi.shape[1] != self.ns + 2:
+            raise ValueError("phi must be [n, %d]" % (self.ns + 2))
+        phi_out, h, na, nr, st = self._outs(n, h_io, out)
+        _check(lib().chem_integrate_noalloc(self._h, n, float(dt),
+                                            _ptr(phi, torch.float64, self.device, name="phi"),
+                                            _ptr(phi_out, torch.float64, self.device, n * (self.ns + 2), "out"),
+                                            _ptr(h, torch.float64, self.device, n, "h_io"),
+                                            _ptr(na), _ptr(nr), _ptr(st), _stream(self.device)))
         return Result(phi_out, h, na, nr, st)
 
     # ---- zonal reference mapping ----

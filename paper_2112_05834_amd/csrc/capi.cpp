@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -61,6 +62,43 @@ constexpr size_t kMaxLds = 160 * 1024;
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Static device scratch of the allocation-free entry point
+// (chem_integrate_noalloc): control words first (the persistent queue head),
+// then the workgroup kernel's J and M workspace slots. Every GPU the library
+// runs on holds its own copy until the process ends. In host code the name
+// `scratch` stands for the array only as a symbol: kernels and copies get the
+// device address looked up for the current device, never the name itself.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchBytes = CHEM_NOALLOC_SCRATCH_BYTES;
+static_assert(kScratchBytes % 256 == 0, "scratch size");
+constexpr size_t kScratchCtl = 256;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<unsigned char*> g_scratch_addr;   // per device
+
+// The address of `scratch` on device dev, which must be current. Looked up
+// once per device; later calls return the kept address.
+int scratch_address(int dev, unsigned char** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_addr.size() <= static_cast<size_t>(dev)) g_scratch_addr.resize(dev + 1, nullptr);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(CHEM_EHIP, "hipGetSymbolAddress(scratch) returned a null address");
+    g_scratch_addr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return CHEM_OK;
+}
+}  // namespace
+
 struct chem_solver {
   int dev = 0;
   int cus = 0;
@@ -73,6 +111,7 @@ struct chem_solver {
   double* d_nasa = nullptr;
   double* d_W = nullptr;
   unsigned long long* d_head = nullptr;   // [0] queue head, [1] log head
+  unsigned char* scratch = nullptr;       // this device's address of the static scratch array
   chemk::Variant variants[8];
   int nvariants = 0;
   chem::Work work{};
@@ -264,6 +303,7 @@ int chem_solver_create(const chem_mech* m, const chem_opts* o, int32_t dev, chem
     if (s->wide_lds > kMaxLds)
       return fail(CHEM_EUNSUPPORTED, "mechanism and one cell's work area exceed the 160 KB LDS");
   }
+  if (int rc = scratch_address(dev, &s->scratch)) return rc;
   HIP_TRY(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
   *out = s.release();
   return CHEM_OK;
@@ -415,10 +455,20 @@ int ensure_ws(chem_solver* s) {
   return CHEM_OK;
 }
 
-// One chemistry step with the solver's options on stream st.
+// Queue head and workgroup workspace taken from the static scratch instead
+// of the solver's own buffers (the allocation-free entry point).
+struct StaticRes {
+  unsigned long long* head = nullptr;
+  double* ws = nullptr;
+  long long slots = 0;
+};
+
+// One chemistry step with the solver's options on stream st. With res, the
+// queue head and workspace come from there, and no log record or timing
+// event is made.
 int launch_step(chem_solver* s, const chem_opts& o, int64_t n, double dt, const double* in, double* out,
                 double* h_io, int32_t* n_acc, int32_t* n_rej, int8_t* status, int accumulate,
-                const int* perm, hipStream_t st, bool head_set = false) {
+                const int* perm, hipStream_t st, bool head_set = false, const StaticRes* res = nullptr) {
   Shape sh;
   if (int rc = pick_shape(s, o, sh)) return rc;
   chemk::IntegrateArgs a{};
@@ -438,24 +488,28 @@ int launch_step(chem_solver* s, const chem_opts& o, int64_t n, double dt, const 
   a.cell_doubles = chemk::cell_doubles(sh.v.nn, s->nr, s->ns);
   a.wpb = sh.wpb;
   a.perm = perm;
-  a.head = s->d_head;
+  unsigned long long* const head = res ? res->head : s->d_head;
+  a.head = head;
   a.chunk = o.queue_chunk > 0 ? o.queue_chunk : 1;
-  a.log.cap = s->log_cap;
-  a.log.feats = s->log_feats;
-  a.log.target = s->log_target;
-  a.log.head = s->d_head + 1;
+  if (!res) {
+    a.log.cap = s->log_cap;
+    a.log.feats = s->log_feats;
+    a.log.target = s->log_target;
+    a.log.head = s->d_head + 1;
+  }
   const bool persistent = o.schedule != CHEM_PLAIN;
   const long long per_block = static_cast<long long>(sh.wpb) * sh.cpw;
   long long grid;
   if (s->wide) {
-    if (!s->d_ws) return fail(CHEM_ESTATE, "workspace not allocated");
-    a.ws = s->d_ws;
+    double* const ws = res ? res->ws : s->d_ws;
+    if (!ws) return fail(CHEM_ESTATE, "workspace not allocated");
+    a.ws = ws;
     a.ws_stride = s->ws_stride;
     a.ld = s->ld;
-    grid = s->wide_slots;
+    grid = res ? res->slots : s->wide_slots;
     if (o.blocks > 0 && o.blocks < grid) grid = o.blocks;
     if (grid > n) grid = n;
-    if (persistent && !head_set) HIP_TRY(chemk::launch_fill_u64(s->d_head, 0ull, st), "queue reset");
+    if (persistent && !head_set) HIP_TRY(chemk::launch_fill_u64(head, 0ull, st), "queue reset");
   } else if (!persistent) {
     grid = (n + per_block - 1) / per_block;
   } else {
@@ -464,13 +518,13 @@ int launch_step(chem_solver* s, const chem_opts& o, int64_t n, double dt, const 
     grid = o.blocks > 0 ? o.blocks : static_cast<long long>(s->cus) * bpc;
     const long long need = (n + per_block - 1) / per_block;
     if (grid > need) grid = need;
-    if (!head_set) HIP_TRY(chemk::launch_fill_u64(s->d_head, 0ull, st), "queue reset");
+    if (!head_set) HIP_TRY(chemk::launch_fill_u64(head, 0ull, st), "queue reset");
   }
   if (grid < 1) return CHEM_OK;
   if (grid > 0x7fffffffLL) return fail(CHEM_EINVAL, "too many cells for one launch");
   bool timed = false;
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-  if (s->timing) {
+  if (s->timing && !res) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(st, &cs), "hipStreamIsCapturing");
     if (cs == hipStreamCaptureStatusNone) {
@@ -524,6 +578,36 @@ int chem_integrate(chem_solver* s, int64_t n, double dt, const double* in, doubl
     if (int rc = binned_perm(s, n, dt, in, st, &perm)) return rc;
   }
   return launch_step(s, s->opts, n, dt, in, out, h_io, n_acc, n_rej, status, 0, perm, st);
+}
+
+// chem_integrate on the persistent queue in index order, with the queue head
+// and the workgroup kernel's workspace in the static scratch: nothing is
+// allocated or freed here, and no allocating runtime call is made.
+int chem_integrate_noalloc(chem_solver* s, int64_t n, double dt, const double* in, double* out, double* h_io,
+                           int32_t* n_acc, int32_t* n_rej, int8_t* status, void* stream) {
+  if (int rc = check_integrate_args(s, n, dt, in, out)) return rc;
+  if (n == 0) return CHEM_OK;
+  if (!s->scratch) return fail(CHEM_ESTATE, "chem_integrate_noalloc: no scratch address for this device");
+  DeviceGuard g(s->dev);
+  StaticRes res;
+  res.head = reinterpret_cast<unsigned long long*>(s->scratch);
+  if (s->wide) {
+    const size_t slot = static_cast<size_t>(s->ws_stride) * sizeof(double);
+    const size_t room = kScratchBytes - kScratchCtl;
+    if (slot > room)
+      return fail(CHEM_EUNSUPPORTED, "chem_integrate_noalloc: one cell's workspace (" + std::to_string(slot) +
+                                         " bytes) exceeds the static scratch (" + std::to_string(room) + " bytes)");
+    int bpc = chemk::integrate_wide_blocks_per_cu(true, s->wide_lds);
+    if (bpc < 1) bpc = 1;
+    const long long resident = static_cast<long long>(s->cus) * bpc;
+    const long long fit = static_cast<long long>(room / slot);
+    res.ws = reinterpret_cast<double*>(s->scratch + kScratchCtl);
+    res.slots = resident < fit ? resident : fit;
+  }
+  chem_opts o = s->opts;
+  o.schedule = CHEM_PERSISTENT;
+  return launch_step(s, o, n, dt, in, out, h_io, n_acc, n_rej, status, 0, nullptr, static_cast<hipStream_t>(stream),
+                     false, &res);
 }
 
 }  // extern "C"
