@@ -53,6 +53,22 @@ extern "C" {
 #define CHEM_CELL_SINGULAR 4    /* exact zero pivot in the LU of M            */
 #define CHEM_CELL_T_RANGE 5     /* an accepted step left T in [200, 6000] K   */
 
+/* Rosenbrock schemes (the paper leaves the scheme unnamed), both in the
+ * transformed form with M = I/(gamma h) - J: Rodas3 (Sandu et al. 1997, order
+ * 3 with embedded order 2, L-stable) and ROS4 (Shampine 1982, order 4 with
+ * embedded order 3, A-stable). Both take two new right-hand sides per
+ * attempted step; the step factor goes as err^(-1/3) and err^(-1/4). */
+#define CHEM_RODAS3 0
+#define CHEM_ROS4 1
+
+/* How J is obtained (paper: Introduction and Methodology, the Analytical
+ * Jacobian paragraph; Fig. 2): analytically, or by forward differences as
+ * conventional ODE codes do, one more right-hand side per state component
+ * (column j from the step d_j = (y_j + s_j) - y_j, s_j = sqrt(2^-53
+ * max(1e-5, |y_j|))). */
+#define CHEM_JAC_ANALYTICAL 0
+#define CHEM_JAC_FD 1
+
 /* Schedules. */
 #define CHEM_PLAIN 0              /* one launch per chemistry step, static cell-to-wave map */
 #define CHEM_PERSISTENT 1         /* resident waves pull cells from an atomic queue          */
@@ -71,6 +87,8 @@ typedef struct {
   int32_t blocks;           /* persistent grid size in blocks; 0 = fill the device       */
   int32_t waves_per_block;  /* 0 = auto                                                  */
   int64_t hbm_budget_bytes; /* workspace budget for in-flight cells; 0 = 50% of free     */
+  int32_t scheme;           /* CHEM_RODAS3 (default) or CHEM_ROS4                        */
+  int32_t jacobian;         /* CHEM_JAC_ANALYTICAL (default) or CHEM_JAC_FD              */
 } chem_opts;
 
 /* Fill o with the defaults above. Paper: Results and discussion (the Spray A
@@ -199,6 +217,19 @@ int chem_eval_rhs_jac(chem_solver* s, int64_t n_cells, const double* phi, double
  * b[batch][n] in place. n must equal the solver's state size. */
 int chem_lu_batch(chem_solver* s, int64_t batch, double* A, int32_t* piv, int32_t* info,
                   double* b, void* stream);
+/* Paper: Methodology, the Analytical Jacobian paragraph (LAPACK's LU and back
+ * substitution) and Fig. 2. The vendor routine for comparison with the
+ * library's own LU, not used by any integration: rocSOLVER's
+ * dgetrf_strided_batched, then, if b is not NULL, dgetrs_strided_batched for
+ * one right-hand side, on batch column-major n x n matrices A (device,
+ * [batch][n][n] with element (i, j) at j n + i) in place. piv: device int32
+ * [batch][n], LAPACK's 1-based interchanges; info: device int32 [batch];
+ * b: device [batch][n] or NULL. Enqueued on stream, on the current HIP
+ * device. rocSOLVER and rocBLAS are loaded at the first call (dlopen) and a
+ * rocBLAS handle is kept per device. Errors: CHEM_EINVAL, CHEM_EUNSUPPORTED
+ * (the libraries cannot be loaded), CHEM_EHIP. */
+int chem_lu_batch_rocsolver(int32_t n, int64_t batch, double* A, int32_t* piv, int32_t* info,
+                            double* b, void* stream);
 
 /* ---- learned cost model (changes scheduling only, never results) ------- */
 /* Paper for every call of this block: Methodology, DLBFoam paragraph (a

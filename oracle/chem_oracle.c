@@ -498,6 +498,27 @@ void orc_jac(const orc_mech* m, double p, const double* y, double* J) {
   free(D);
 }
 
+/* Forward differences, one more f per column: the way ODE codes form J
+ * when no analytical Jacobian is given (paper: Introduction, the costly
+ * finite-difference Jacobian; Fig. 2). The increment rule s_j =
+ * sqrt(u max(1e-5, |y_j|)) is the one of Hairer and Wanner's Rosenbrock
+ * codes; the divisor is the step actually taken, (y_j + s_j) - y_j. */
+#define FD_UROUND 1.1102230246251565e-16
+void orc_jac_fd(const orc_mech* m, double p, const double* y, const double* f0, double* J) {
+  int n = m->ns + 1;
+  double* yp = (double*)malloc(sizeof(double) * 2 * n);
+  double* fp = yp + n;
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) yp[i] = y[i];
+    double s = sqrt(FD_UROUND * fmax(1e-5, fabs(y[j])));
+    yp[j] = y[j] + s;
+    double d = yp[j] - y[j];
+    orc_rhs(m, p, yp, fp);
+    for (int i = 0; i < n; ++i) J[(size_t)i * n + j] = (fp[i] - f0[i]) / d;
+  }
+  free(yp);
+}
+
 /* ------------------------------------------------------------------------ */
 /* dense LU with partial pivoting (getrf / getrs semantics)                  */
 /* ------------------------------------------------------------------------ */
@@ -559,6 +580,8 @@ typedef struct {
   double gamma;
   double a[4][4], c[4][4]; /* strictly lower, row = stage */
   double m[4], e[4];
+  int est_order;           /* order of the embedded solution: the error
+                              estimate is O(h^(est_order+1)) */
 } tableau_t;
 
 /* Rodas3 (Sandu et al. 1997): order 3, embedded order 2, L-stable, stiffly
@@ -568,7 +591,8 @@ static const tableau_t RODAS3 = {
     {{0, 0, 0, 0}, {0, 0, 0, 0}, {2, 0, 0, 0}, {2, 0, 1, 0}},
     {{0, 0, 0, 0}, {4, 0, 0, 0}, {1, -1, 0, 0}, {1, -1, -8.0 / 3.0, 0}},
     {2, 0, 1, 1},
-    {0, 0, 0, 1}};
+    {0, 0, 0, 1},
+    2};
 
 /* ROS4 of Shampine (1982), the first coefficient set of Hairer and Wanner's
  * Rosenbrock code family: order 4, embedded order 3, gamma = 1/2. Stage 4
@@ -578,7 +602,8 @@ static const tableau_t ROS4 = {
     {{0, 0, 0, 0}, {2, 0, 0, 0}, {48.0 / 25.0, 6.0 / 25.0, 0, 0}, {48.0 / 25.0, 6.0 / 25.0, 0, 0}},
     {{0, 0, 0, 0}, {-8, 0, 0, 0}, {372.0 / 25.0, 12.0 / 5.0, 0, 0}, {-112.0 / 125.0, -54.0 / 125.0, -2.0 / 5.0, 0}},
     {19.0 / 9.0, 1.0 / 2.0, 25.0 / 108.0, 125.0 / 108.0},
-    {17.0 / 54.0, 7.0 / 36.0, 0, 125.0 / 108.0}};
+    {17.0 / 54.0, 7.0 / 36.0, 0, 125.0 / 108.0},
+    3};
 
 static const tableau_t* tableau_of(int scheme) {
   if (scheme == ORC_RODAS3) return &RODAS3;
@@ -723,7 +748,8 @@ static int integrate_cell(const orc_mech* m, double p, double dt, const orc_opts
     if (attempts >= o->max_steps) { status = ORC_MAX_STEPS; break; }
     if (need_start) {
       orc_rhs(m, p, y, w->f0);
-      orc_jac(m, p, y, w->J);
+      if (o->jacobian == ORC_JAC_FD) orc_jac_fd(m, p, y, w->f0, w->J);
+      else orc_jac(m, p, y, w->J);
       need_start = 0;
     }
     double rem = dt - t;
@@ -750,7 +776,12 @@ static int integrate_cell(const orc_mech* m, double p, double dt, const orc_opts
       err = INFINITY;
       hnew = hc * FAC_REJ;
     } else {
-      double fac = FAC_SAFE / cbrt(fmax(err, 1e-10));
+      /* err is O(h^(q+1)) for an embedded solution of order q, so the step
+       * factor goes as err^(-1/(q+1)): a cube root for Rodas3 (q = 2), a
+       * fourth root for ROS4 (q = 3), taken as two correctly rounded square
+       * roots */
+      const double ef = fmax(err, 1e-10);
+      double fac = FAC_SAFE / (tb->est_order == 3 ? sqrt(sqrt(ef)) : cbrt(ef));
       fac = fmin(FAC_MAX, fmax(FAC_MIN, fac));
       hnew = hc * fac;
     }
@@ -825,7 +856,8 @@ static void* worker(void* arg) {
 int orc_integrate(const orc_mech* m, long n_cells, double dt, const orc_opts* o,
                   const double* phi_in, double* phi_out, double* h_io, int* n_acc, int* n_rej,
                   signed char* status, int n_threads) {
-  if (!m || !o || n_cells < 0 || !(dt > 0.0) || (n_cells > 0 && (!phi_in || !phi_out)) || !tableau_of(o->scheme)) {
+  if (!m || !o || n_cells < 0 || !(dt > 0.0) || (n_cells > 0 && (!phi_in || !phi_out)) || !tableau_of(o->scheme) ||
+      (o->jacobian != ORC_JAC_ANALYTICAL && o->jacobian != ORC_JAC_FD)) {
     snprintf(g_err, sizeof g_err, "orc_integrate: bad argument");
     return -1;
   }

@@ -38,7 +38,12 @@ typedef struct {
   double atol;      /* absolute tolerance, same for T and every Y */
   int max_steps;    /* attempted steps per cell per call */
   int scheme;       /* ORC_RODAS3 (0) or ORC_ROS4 (1) */
+  int jacobian;     /* ORC_JAC_ANALYTICAL (0) or ORC_JAC_FD (1) */
 } orc_opts;
+
+/* How the integrator obtains J: analytically, or by forward differences
+ * (the conventional way the paper's analytical Jacobian replaces). */
+enum { ORC_JAC_ANALYTICAL = 0, ORC_JAC_FD = 1 };
 
 /* Rosenbrock schemes (the paper leaves the scheme unnamed). */
 enum { ORC_RODAS3 = 0, ORC_ROS4 = 1 };
@@ -67,6 +72,10 @@ void orc_omega(const orc_mech* m, double T, double p, const double* Y, double* o
 void orc_rhs(const orc_mech* m, double p, const double* y, double* f);
 /* Analytical Jacobian df/dy, row-major n x n. */
 void orc_jac(const orc_mech* m, double p, const double* y, double* J);
+/* Forward-difference Jacobian, row-major n x n, from f0 = f(y): column j is
+ * (f(y + d_j e_j) - f0) / d_j with d_j = (y_j + s_j) - y_j and
+ * s_j = sqrt(u max(1e-5, |y_j|)), u = 2^-53. */
+void orc_jac_fd(const orc_mech* m, double p, const double* y, const double* f0, double* J);
 
 /* In-place LU with partial pivoting of a row-major n x n matrix. piv[k] is the
  * row swapped with row k at step k (0-based). Returns 0, or k+1 if the pivot of

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchem.so")
-SOURCES = ["mech.cpp", "capi.cpp", "integrator.hip", "integrator_wide.hip", "model.hip", "zonal.hip"]
+SOURCES = ["mech.cpp", "capi.cpp", "integrator.hip", "integrator_wide.hip", "model.hip", "zonal.hip",
+           "rocsolver_cmp.cpp"]
 ARCH = os.environ.get("CHEM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -39,7 +40,7 @@ def build(verbose=False, jobs=4):
         if p0.wait() != 0:
             raise RuntimeError("hipcc failed on " + src0)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + [_obj(s) for s in SOURCES]
+    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + [_obj(s) for s in SOURCES] + ["-ldl"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

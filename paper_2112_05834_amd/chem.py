@@ -17,6 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libchem.so")
 
 PLAIN, PERSISTENT, PERSISTENT_BINNED = 0, 1, 2
+RODAS3, ROS4 = 0, 1
+JAC_ANALYTICAL, JAC_FD = 0, 1
 CELL_OK, CELL_MAX_STEPS, CELL_H_UNDERFLOW, CELL_NONFINITE, CELL_SINGULAR, CELL_T_RANGE = range(6)
 
 _ERRORS = {-1: "CHEM_EINVAL", -2: "CHEM_EMECH", -3: "CHEM_EHIP", -4: "CHEM_ENOMEM", -5: "CHEM_ESTATE",
@@ -33,7 +35,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("max_steps", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("cells_per_wave", ctypes.c_int32),
                 ("queue_chunk", ctypes.c_int32), ("blocks", ctypes.c_int32),
-                ("waves_per_block", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64)]
+                ("waves_per_block", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
+                ("scheme", ctypes.c_int32), ("jacobian", ctypes.c_int32)]
 
 
 class TrainOpts(ctypes.Structure):
@@ -72,6 +75,7 @@ def lib():
             "chem_integrate_noalloc": (i32, [_vp, i64, dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "chem_eval_rhs_jac": (i32, [_vp, i64, _vp, _vp, _vp, _vp]),
             "chem_lu_batch": (i32, [_vp, i64, _vp, _vp, _vp, _vp, _vp]),
+            "chem_lu_batch_rocsolver": (i32, [i32, i64, _vp, _vp, _vp, _vp, _vp]),
             "chem_log_enable": (i32, [_vp, i64]),
             "chem_log_fetch": (i32, [_vp, _vp, _vp, ctypes.POINTER(i64), _vp]),
             "chem_features": (i32, [_vp, i64, dbl, _vp, _vp, _vp]),
@@ -146,6 +150,20 @@ def _ptr(t: Optional[torch.Tensor], dtype=None, device=None, numel=None, name="t
 
 def _stream(device: torch.device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def lu_batch_rocsolver(A: torch.Tensor, b: Optional[torch.Tensor] = None):
+    """chem_lu_batch_rocsolver: rocSOLVER's batched LU (and solve of b [batch,
+    n]) in place on A [batch, n, n] holding column-major matrices (A[k, j, i] =
+    element (i, j)). Returns (A, piv 1-based, info, b)."""
+    batch, n = A.shape[0], A.shape[1]
+    dev = A.device
+    piv = torch.empty((batch, n), dtype=torch.int32, device=dev)
+    info = torch.empty(batch, dtype=torch.int32, device=dev)
+    with torch.cuda.device(dev):
+        _check(lib().chem_lu_batch_rocsolver(n, batch, _ptr(A, torch.float64, dev, batch * n * n, "A"), _ptr(piv),
+                                             _ptr(info), _ptr(b, torch.float64, dev, batch * n, "b"), _stream(dev)))
+    return A, piv, info, b
 
 
 class Mechanism:

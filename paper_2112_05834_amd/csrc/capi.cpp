@@ -173,6 +173,10 @@ unsigned long long fnv1a(const void* p, size_t n, unsigned long long h) {
   return h;
 }
 
+namespace chem {
+void set_last_error(const std::string& msg) { g_err = msg; }
+}  // namespace chem
+
 extern "C" {
 
 const char* chem_last_error(void) { return g_err.c_str(); }
@@ -228,6 +232,9 @@ static int check_opts(const chem_opts* o) {
   if (o->queue_chunk < 0 || o->blocks < 0 || o->waves_per_block < 0 || o->waves_per_block > 4 ||
       o->hbm_budget_bytes < 0)
     return fail(CHEM_EINVAL, "negative launch option or waves_per_block > 4");
+  if (o->scheme != CHEM_RODAS3 && o->scheme != CHEM_ROS4) return fail(CHEM_EINVAL, "unknown scheme");
+  if (o->jacobian != CHEM_JAC_ANALYTICAL && o->jacobian != CHEM_JAC_FD)
+    return fail(CHEM_EINVAL, "unknown jacobian mode");
   return CHEM_OK;
 }
 
@@ -476,6 +483,8 @@ int launch_step(chem_solver* s, const chem_opts& o, int64_t n, double dt, const 
   a.o.rtol = o.rtol;
   a.o.atol = o.atol;
   a.o.max_steps = o.max_steps;
+  a.o.scheme = o.scheme;
+  a.o.jac_fd = o.jacobian == CHEM_JAC_FD;
   a.dt = dt;
   a.n = n;
   a.phi_in = in;

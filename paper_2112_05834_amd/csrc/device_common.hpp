@@ -18,16 +18,91 @@ constexpr double kPatm = 101325.0;     // Pa
 constexpr double kLn10 = 2.302585092994045684;
 constexpr int kBig = 1 << 20;
 
-// Rodas3 in the transformed form (unknowns u_i, matrix I/(gamma h) - J):
-// u_s = M^-1 ( f(y + sum_j a_sj u_j) + sum_j (c_sj / h) u_j ), y_new = y + sum m_j u_j,
-// error estimate u_4.
-constexpr double kGamma = 0.5;
-constexpr double kA31 = 2.0, kA41 = 2.0, kA43 = 1.0;
-constexpr double kC21 = 4.0, kC31 = 1.0, kC32 = -1.0, kC41 = 1.0, kC42 = -1.0;
-constexpr double kC43 = -8.0 / 3.0;
+// Forward-difference Jacobian (the conventional alternative to the
+// analytical one): column j is (f(y + d_j e_j) - f(y)) / d_j with
+// d_j = (y_j + s_j) - y_j, the step actually taken, and
+// s_j = sqrt(u max(1e-5, |y_j|)), u = 2^-53 (the increment rule of Hairer and
+// Wanner's Rosenbrock codes).
+constexpr double kFdUround = 1.1102230246251565e-16;
+__device__ __forceinline__ double fd_increment(double yj) { return sqrt(kFdUround * fmax(1e-5, fabs(yj))); }
+
 // step-size controller
 constexpr double kFacMin = 0.2, kFacMax = 6.0, kFacSafe = 0.9, kFacRej = 0.1;
 constexpr double kHMin = 1e-20, kTMin = 200.0, kTMax = 6000.0;
+
+// Four-stage Rosenbrock schemes in the transformed form (unknowns u_i,
+// matrix M = I/(gamma h) - J):
+//   u_s = M^-1 ( f(y + sum_{j<s} a_sj u_j) + sum_{j<s} (c_sj / h) u_j ),
+//   y_new = y + sum_j m_j u_j,  error estimate sum_j e_j u_j.
+// fsrc[s] says where stage s takes f from: kFy = f(y) (a zero a-row), kFprev =
+// the previous stage's f (the same a-row, so the same argument), kFnew = a new
+// evaluation. Sums run over every j in ascending order, zero coefficients
+// included, so that the operations match the oracle's. est_order is the order
+// of the embedded solution (the step factor goes as err^(-1/(est_order+1))).
+constexpr int kFy = 0, kFprev = 1, kFnew = 2;
+constexpr int kRodas3 = 0, kRos4 = 1;
+
+template <int SCHEME>
+struct Tab;
+
+// Rodas3 (Sandu et al. 1997): order 3(2), L-stable, stiffly accurate.
+template <>
+struct Tab<kRodas3> {
+  static constexpr double gamma = 0.5;
+  static constexpr double a[4][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {2, 0, 0, 0}, {2, 0, 1, 0}};
+  static constexpr double c[4][4] = {{0, 0, 0, 0}, {4, 0, 0, 0}, {1, -1, 0, 0}, {1, -1, -8.0 / 3.0, 0}};
+  static constexpr double m[4] = {2, 0, 1, 1};
+  static constexpr double e[4] = {0, 0, 0, 1};
+  static constexpr int fsrc[4] = {kFy, kFy, kFnew, kFnew};
+  static constexpr int est_order = 2;
+};
+
+// ROS4 of Shampine (1982): order 4(3), gamma = 1/2, A-stable.
+template <>
+struct Tab<kRos4> {
+  static constexpr double gamma = 0.5;
+  static constexpr double a[4][4] = {
+      {0, 0, 0, 0}, {2, 0, 0, 0}, {48.0 / 25.0, 6.0 / 25.0, 0, 0}, {48.0 / 25.0, 6.0 / 25.0, 0, 0}};
+  static constexpr double c[4][4] = {{0, 0, 0, 0},
+                                     {-8, 0, 0, 0},
+                                     {372.0 / 25.0, 12.0 / 5.0, 0, 0},
+                                     {-112.0 / 125.0, -54.0 / 125.0, -2.0 / 5.0, 0}};
+  static constexpr double m[4] = {19.0 / 9.0, 1.0 / 2.0, 25.0 / 108.0, 125.0 / 108.0};
+  static constexpr double e[4] = {17.0 / 54.0, 7.0 / 36.0, 0, 125.0 / 108.0};
+  static constexpr int fsrc[4] = {kFy, kFnew, kFnew, kFprev};
+  static constexpr int est_order = 3;
+};
+
+// Coefficient (s, j) of a stage index s known only at run time (s is
+// uniform over the cell's lanes): a select over the four compile-time rows.
+template <int SCHEME>
+__device__ __forceinline__ double tab_a(int s, int j) {
+  using T = Tab<SCHEME>;
+  return s == 1 ? T::a[1][j] : (s == 2 ? T::a[2][j] : (s == 3 ? T::a[3][j] : T::a[0][j]));
+}
+template <int SCHEME>
+__device__ __forceinline__ double tab_c(int s, int j) {
+  using T = Tab<SCHEME>;
+  return s == 1 ? T::c[1][j] : (s == 2 ? T::c[2][j] : (s == 3 ? T::c[3][j] : T::c[0][j]));
+}
+template <int SCHEME>
+__device__ __forceinline__ int tab_fsrc(int s) {
+  using T = Tab<SCHEME>;
+  return s == 1 ? T::fsrc[1] : (s == 2 ? T::fsrc[2] : (s == 3 ? T::fsrc[3] : T::fsrc[0]));
+}
+
+// Step factor from the error norm (before the [kFacMin, kFacMax] clamp):
+// kFacSafe err^(-1/(q+1)), the fourth root as two correctly rounded square
+// roots.
+template <int SCHEME>
+__device__ __forceinline__ double step_factor(double err) {
+  const double ef = fmax(err, 1e-10);
+  if constexpr (Tab<SCHEME>::est_order == 3) {
+    return kFacSafe / sqrt(sqrt(ef));
+  } else {
+    return kFacSafe / cbrt(ef);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // mechanism in LDS

@@ -495,6 +495,28 @@ struct Cell {
     return f;
   }
 
+  // Jacobian by forward differences, written row-major into ca.J: one more
+  // right-hand side per state component (f0 = f(y) given). Every lane holds
+  // its component of the perturbed state; lane j adds the increment.
+  __device__ static void fd_jacobian(const MechArgs& A, const MechLds& L, const CellArea& ca, double p, double y,
+                                     double f0) {
+    const int n = A.ns + 1;
+    const int i = Gp::gl();
+    if (i < NN) {
+#pragma unroll
+      for (int j = 0; j < NN; ++j) ca.J[i * NN + j] = 0.0;
+    }
+#pragma nounroll
+    for (int j = 0; j < n; ++j) {
+      const double yj = Gp::bcast(y, j);
+      const double yp = yj + fd_increment(yj);
+      const double d = yp - yj;
+      const double fj = rhs<false>(A, L, ca, p, i == j ? yp : y);
+      if (i < NN) ca.J[i * NN + j] = (fj - f0) / d;
+    }
+    wsync();
+  }
+
   // -------------------------------------------------------------------------
   // LU with partial pivoting of the rows in registers (row = lane). Rows are
   // not moved during the elimination: pos tracks each row's LAPACK position,
@@ -595,11 +617,14 @@ struct Cell {
   }
 
   // -------------------------------------------------------------------------
-  // adaptive Rodas3 over [0, dt] for one cell (y: this lane's component)
+  // adaptive Rosenbrock integration (scheme SCHEME) over [0, dt] for one cell
+  // (y: this lane's component)
   // -------------------------------------------------------------------------
+  template <int SCHEME>
   __device__ static __forceinline__ void integrate(const MechArgs& A, const MechLds& L, const CellArea& ca,
                                                    const OptsDev& o, double p, double dt, double& y,
                                                    double& hio, int& nacc_o, int& nrej_o, int& status_o) {
+    using TB = Tab<SCHEME>;
     const int ns = A.ns;
     const int n = ns + 1;
     const int i = Gp::gl();
@@ -621,7 +646,12 @@ struct Cell {
         break;
       }
       if (need) {
-        f0 = rhs<true>(A, L, ca, p, y);
+        if (o.jac_fd) {
+          f0 = rhs<false>(A, L, ca, p, y);
+          fd_jacobian(A, L, ca, p, y, f0);
+        } else {
+          f0 = rhs<true>(A, L, ca, p, y);
+        }
         need = false;
       }
       const double rem = dt - t;
@@ -635,7 +665,7 @@ struct Cell {
         status = 2;
         break;
       }
-      const double g = 1.0 / (kGamma * hc);
+      const double g = 1.0 / (TB::gamma * hc);
       if (i < NN) {
 #pragma unroll
         for (int j = 0; j < NN; ++j) M[j] = (i == j ? g : 0.0) - ca.J[i * NN + j];
@@ -649,25 +679,27 @@ struct Cell {
         status = 4;
         break;
       }
-      // stages: one right-hand side and one solve call site for all four
+      // stages: one right-hand side and one solve call site for all four;
+      // every sum runs over j < st in ascending order with the scheme's
+      // coefficients, zeros included, as the oracle forms it
       double u1 = 0.0, u2 = 0.0, u3 = 0.0, u4 = 0.0;
+      double fs = f0;
 #pragma nounroll
       for (int st = 0; st < 4; ++st) {
-        double v;
-        if (st == 0) {
-          v = f0;
-        } else if (st == 1) {
-          v = f0 + (kC21 / hc) * u1;
-        } else {
-          const bool s3 = st == 2;
-          double ys = y + (s3 ? kA31 : kA41) * u1;
-          ys = ys + 0.0 * u2;
-          if (!s3) ys = ys + kA43 * u3;
-          const double fs = rhs<false>(A, L, ca, p, ys);
-          v = fs + ((s3 ? kC31 : kC41) / hc) * u1;
-          v = v + ((s3 ? kC32 : kC42) / hc) * u2;
-          if (!s3) v = v + (kC43 / hc) * u3;
+        const int src = tab_fsrc<SCHEME>(st);
+        if (src == kFnew) {
+          double ys = y;
+          if (st > 0) ys = ys + tab_a<SCHEME>(st, 0) * u1;
+          if (st > 1) ys = ys + tab_a<SCHEME>(st, 1) * u2;
+          if (st > 2) ys = ys + tab_a<SCHEME>(st, 2) * u3;
+          fs = rhs<false>(A, L, ca, p, ys);
+        } else if (src == kFy) {
+          fs = f0;
         }
+        double v = fs;
+        if (st > 0) v = v + (tab_c<SCHEME>(st, 0) / hc) * u1;
+        if (st > 1) v = v + (tab_c<SCHEME>(st, 1) / hc) * u2;
+        if (st > 2) v = v + (tab_c<SCHEME>(st, 2) / hc) * u3;
         const double x = solve(M, pos, rdiag, v);
         if (st == 0) u1 = x;
         else if (st == 1) u2 = x;
@@ -675,12 +707,16 @@ struct Cell {
         else u4 = x;
       }
       // new solution and error estimate
-      double yn = y + 2.0 * u1;
-      yn = yn + 0.0 * u2;
-      yn = yn + 1.0 * u3;
-      yn = yn + 1.0 * u4;
+      double yn = y + TB::m[0] * u1;
+      yn = yn + TB::m[1] * u2;
+      yn = yn + TB::m[2] * u3;
+      yn = yn + TB::m[3] * u4;
+      double ev = 0.0 + TB::e[0] * u1;
+      ev = ev + TB::e[1] * u2;
+      ev = ev + TB::e[2] * u3;
+      ev = ev + TB::e[3] * u4;
       const double sc = o.atol + o.rtol * fmax(fabs(y), fabs(yn));
-      const double q = u4 / sc;
+      const double q = ev / sc;
       const double acc = Gp::sum(valid ? q * q : 0.0);
       double err = sqrt(acc / n);
       double hnew;
@@ -688,7 +724,7 @@ struct Cell {
         err = INFINITY;
         hnew = hc * kFacRej;
       } else {
-        double fac = kFacSafe / cbrt(fmax(err, 1e-10));
+        double fac = step_factor<SCHEME>(err);
         fac = fmin(kFacMax, fmax(kFacMin, fac));
         hnew = hc * fac;
       }
@@ -738,7 +774,7 @@ __device__ __forceinline__ void cell_features(int ns, double y, double p, double
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-template <int NN, int G>
+template <int NN, int G, int SCHEME>
 __device__ __forceinline__ void run_cell(const IntegrateArgs& a, const MechLds& L, const CellArea& ca,
                                          long long cell) {
   using C = Cell<NN, G>;
@@ -752,7 +788,7 @@ __device__ __forceinline__ void run_cell(const IntegrateArgs& a, const MechLds& 
   if (a.log.cap > 0) cell_features<G>(ns, y, p, a.dt, ft);
   double h = a.h_io ? a.h_io[cell] : 0.0;
   int nacc, nrej, st;
-  C::integrate(a.m, L, ca, a.o, p, a.dt, y, h, nacc, nrej, st);
+  C::template integrate<SCHEME>(a.m, L, ca, a.o, p, a.dt, y, h, nacc, nrej, st);
   double* pout = a.phi_out + cell * w2;
   if (i == 0) {
     pout[0] = y;
@@ -787,7 +823,7 @@ __device__ __forceinline__ void run_cell(const IntegrateArgs& a, const MechLds& 
 template <int NN>
 constexpr int max_waves_per_eu() { return NN >= 32 ? 1 : 2; }
 
-template <int NN, int G, bool PERSIST>
+template <int NN, int G, bool PERSIST, int SCHEME>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, max_waves_per_eu<NN>())))
 k_integrate(IntegrateArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -801,7 +837,7 @@ k_integrate(IntegrateArgs a) {
   const CellArea ca = cell_area<NN>(base, a.m.nr, a.m.ns);
   if (!PERSIST) {
     const long long cell = (static_cast<long long>(blockIdx.x) * a.wpb + wave) * CPW + grp;
-    if (cell < a.n) run_cell<NN, G>(a, L, ca, cell);
+    if (cell < a.n) run_cell<NN, G, SCHEME>(a, L, ca, cell);
   } else {
     for (;;) {
       unsigned long long idx = 0;
@@ -811,7 +847,7 @@ k_integrate(IntegrateArgs a) {
       const long long end = min(static_cast<long long>(idx) + a.chunk, a.n);
       for (long long q = static_cast<long long>(idx); q < end; ++q) {
         const long long cell = a.perm ? static_cast<long long>(a.perm[q]) : q;
-        run_cell<NN, G>(a, L, ca, cell);
+        run_cell<NN, G, SCHEME>(a, L, ca, cell);
       }
     }
   }
@@ -921,13 +957,15 @@ int variants_for(int n, Variant* out, int max_out) {
 int cell_doubles(int nn, int nr, int ns) { return cell_doubles_c(nn, nr, ns); }
 
 template <int NN, int G, bool P>
-static void* integrate_fn() {
-  return reinterpret_cast<void*>(&k_integrate<NN, G, P>);
+static void* integrate_fn(int scheme) {
+  return scheme == dev::kRos4 ? reinterpret_cast<void*>(&k_integrate<NN, G, P, dev::kRos4>)
+                              : reinterpret_cast<void*>(&k_integrate<NN, G, P, dev::kRodas3>);
 }
 
-static void* find_integrate(const Variant& v, bool persistent) {
+static void* find_integrate(const Variant& v, bool persistent, int scheme) {
+  if (scheme != dev::kRodas3 && scheme != dev::kRos4) return nullptr;
 #define V(a, b)                                                                                        \
-  if (v.nn == a && v.g == b) return persistent ? integrate_fn<a, b, true>() : integrate_fn<a, b, false>();
+  if (v.nn == a && v.g == b) return persistent ? integrate_fn<a, b, true>(scheme) : integrate_fn<a, b, false>(scheme);
   CHEM_VARIANTS(V)
 #undef V
   return nullptr;
@@ -935,7 +973,7 @@ static void* find_integrate(const Variant& v, bool persistent) {
 
 hipError_t launch_integrate(const Variant& v, bool persistent, int grid, const IntegrateArgs& a,
                             size_t lds_bytes, hipStream_t st) {
-  void* fn = find_integrate(v, persistent);
+  void* fn = find_integrate(v, persistent, a.o.scheme);
   if (!fn) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
   if (e != hipSuccess) return e;
@@ -946,7 +984,7 @@ hipError_t launch_integrate(const Variant& v, bool persistent, int grid, const I
 }
 
 int integrate_blocks_per_cu(const Variant& v, bool persistent, int wpb, size_t lds_bytes) {
-  void* fn = find_integrate(v, persistent);
+  void* fn = find_integrate(v, persistent, dev::kRodas3);
   if (!fn) return 0;
   hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
   int nb = 0;

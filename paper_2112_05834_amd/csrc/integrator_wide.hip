@@ -501,10 +501,13 @@ __device__ void solve_w(const double* M, int n, int ld, const Wide& W, const dou
   }
 }
 
-// ---- adaptive Rodas3 over [0, dt] for one cell (state in W.y) ---------------------
+// ---- adaptive Rosenbrock integration (scheme SCHEME) over [0, dt] for one cell
+// (state in W.y) ---------------------------------------------------------------
+template <int SCHEME>
 __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, double* J, double* M, int ld,
                             const OptsDev& o, double p, double dt, double& hio, int& nacc_o, int& nrej_o,
                             int& status_o) {
+  using TB = Tab<SCHEME>;
   const int n = A.ns + 1;
   const int t = threadIdx.x;
   int status = 0;
@@ -520,7 +523,23 @@ __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, 
       break;
     }
     if (need) {
-      rhs_w<true>(A, L, W, p, W.y, W.f0, J, ld);
+      if (o.jac_fd) {
+        rhs_w<false>(A, L, W, p, W.y, W.f0, nullptr, ld);
+        // forward differences: column j from f(y + d_j e_j), the perturbed
+        // state staged in W.ys and its f in W.fs
+        for (int j = 0; j < n; ++j) {
+          const double yj = W.y[j];
+          const double yp = yj + fd_increment(yj);
+          const double d = yp - yj;
+          if (t < n) W.ys[t] = t == j ? yp : W.y[t];
+          __syncthreads();
+          rhs_w<false>(A, L, W, p, W.ys, W.fs, nullptr, ld);
+          if (t < n) J[j * ld + t] = (W.fs[t] - W.f0[t]) / d;
+          __syncthreads();
+        }
+      } else {
+        rhs_w<true>(A, L, W, p, W.y, W.f0, J, ld);
+      }
       need = false;
     }
     const double rem = dt - tt;
@@ -534,7 +553,7 @@ __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, 
       status = 2;
       break;
     }
-    const double g = 1.0 / (kGamma * hc);
+    const double g = 1.0 / (TB::gamma * hc);
     if (t < ld) {
       // eight independent loads in flight per thread
       for (int c0 = 0; c0 < n; c0 += 8) {
@@ -553,30 +572,23 @@ __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, 
       status = 4;
       break;
     }
+    // stage sums over j < st in ascending order with the scheme's
+    // coefficients, zeros included, as the oracle forms them. W.fs keeps the
+    // last evaluated f for a stage that reuses it.
     for (int st = 0; st < 4; ++st) {
-      if (st >= 2) {
-        const bool s3 = st == 2;
+      const int src = TB::fsrc[st];
+      if (src == kFnew) {
         if (t < n) {
-          double ys = W.y[t] + (s3 ? kA31 : kA41) * W.u[0][t];
-          ys = ys + 0.0 * W.u[1][t];
-          if (!s3) ys = ys + kA43 * W.u[2][t];
+          double ys = W.y[t];
+          for (int j = 0; j < st; ++j) ys = ys + TB::a[st][j] * W.u[j][t];
           W.ys[t] = ys;
         }
         __syncthreads();
         rhs_w<false>(A, L, W, p, W.ys, W.fs, nullptr, ld);
       }
       if (t < n) {
-        double v;
-        if (st == 0) {
-          v = W.f0[t];
-        } else if (st == 1) {
-          v = W.f0[t] + (kC21 / hc) * W.u[0][t];
-        } else {
-          const bool s3 = st == 2;
-          v = W.fs[t] + ((s3 ? kC31 : kC41) / hc) * W.u[0][t];
-          v = v + ((s3 ? kC32 : kC42) / hc) * W.u[1][t];
-          if (!s3) v = v + (kC43 / hc) * W.u[2][t];
-        }
+        double v = src == kFy ? W.f0[t] : W.fs[t];
+        for (int j = 0; j < st; ++j) v = v + (TB::c[st][j] / hc) * W.u[j][t];
         W.v[t] = v;
       }
       __syncthreads();
@@ -584,12 +596,14 @@ __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, 
     }
     double yn = 0.0, q = 0.0;
     if (t < n) {
-      yn = W.y[t] + 2.0 * W.u[0][t];
-      yn = yn + 0.0 * W.u[1][t];
-      yn = yn + 1.0 * W.u[2][t];
-      yn = yn + 1.0 * W.u[3][t];
+      yn = W.y[t];
+      double ev = 0.0;
+      for (int j = 0; j < 4; ++j) {
+        yn = yn + TB::m[j] * W.u[j][t];
+        ev = ev + TB::e[j] * W.u[j][t];
+      }
       const double sc = o.atol + o.rtol * fmax(fabs(W.y[t]), fabs(yn));
-      q = W.u[3][t] / sc;
+      q = ev / sc;
       W.yn[t] = yn;
     }
     const double acc = bsum(t < n ? q * q : 0.0, W.red);
@@ -600,7 +614,7 @@ __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, 
       err = INFINITY;
       hnew = hc * kFacRej;
     } else {
-      double fac = kFacSafe / cbrt(fmax(err, 1e-10));
+      double fac = step_factor<SCHEME>(err);
       fac = fmin(kFacMax, fmax(kFacMin, fac));
       hnew = hc * fac;
     }
@@ -633,6 +647,7 @@ __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, 
   status_o = status;
 }
 
+template <int SCHEME>
 __device__ void run_cell_w(const IntegrateArgs& a, const MechLds& L, const Wide& W, double* J, double* M,
                            long long cell) {
   const int ns = a.m.ns, n = ns + 1, w2 = ns + 2;
@@ -652,7 +667,7 @@ __device__ void run_cell_w(const IntegrateArgs& a, const MechLds& L, const Wide&
   }
   double h = a.h_io ? a.h_io[cell] : 0.0;
   int nacc, nrej, st;
-  integrate_w(a.m, L, W, J, M, a.ld, a.o, p, a.dt, h, nacc, nrej, st);
+  integrate_w<SCHEME>(a.m, L, W, J, M, a.ld, a.o, p, a.dt, h, nacc, nrej, st);
   double* pout = a.phi_out + cell * w2;
   if (t < n) pout[t == 0 ? 0 : 1 + t] = W.y[t];
   if (t == 0) {
@@ -679,7 +694,7 @@ __device__ void run_cell_w(const IntegrateArgs& a, const MechLds& L, const Wide&
 // ---- kernels ---------------------------------------------------------------------
 // Each workgroup owns workspace slot blockIdx.x. Plain: cells blockIdx.x,
 // blockIdx.x + gridDim.x, ... (static); persistent: chunks from the queue.
-template <bool PERSIST>
+template <bool PERSIST, int SCHEME>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_integrate_wide(IntegrateArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   stage_mech(smem, a.m);
@@ -688,7 +703,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
   double* J = a.ws + static_cast<long long>(blockIdx.x) * a.ws_stride;
   double* M = J + static_cast<long long>(a.m.ns + 1) * a.ld;
   if (!PERSIST) {
-    for (long long cell = blockIdx.x; cell < a.n; cell += gridDim.x) run_cell_w(a, L, W, J, M, cell);
+    for (long long cell = blockIdx.x; cell < a.n; cell += gridDim.x) run_cell_w<SCHEME>(a, L, W, J, M, cell);
   } else {
     for (;;) {
       if (threadIdx.x == 0) W.qslot[0] = atomicAdd(a.head, static_cast<unsigned long long>(a.chunk));
@@ -699,7 +714,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
       const long long end = min(static_cast<long long>(idx) + a.chunk, a.n);
       for (long long q = static_cast<long long>(idx); q < end; ++q) {
         const long long cell = a.perm ? static_cast<long long>(a.perm[q]) : q;
-        run_cell_w(a, L, W, J, M, cell);
+        run_cell_w<SCHEME>(a, L, W, J, M, cell);
       }
     }
   }
@@ -770,13 +785,15 @@ __global__ void __launch_bounds__(256) k_lu_wide(LuArgs a) {
 int wide_cell_bytes(int ns, int nr, int ld) { return static_cast<int>(sizeof(double)) * wide_doubles(ns, nr, ld); }
 
 template <bool P>
-static void* wide_fn() {
-  return reinterpret_cast<void*>(&k_integrate_wide<P>);
+static void* wide_fn(int scheme) {
+  return scheme == dev::kRos4 ? reinterpret_cast<void*>(&k_integrate_wide<P, dev::kRos4>)
+                              : reinterpret_cast<void*>(&k_integrate_wide<P, dev::kRodas3>);
 }
 
 hipError_t launch_integrate_wide(bool persistent, int grid, const IntegrateArgs& a, size_t lds_bytes,
                                  hipStream_t st) {
-  void* fn = persistent ? wide_fn<true>() : wide_fn<false>();
+  if (a.o.scheme != dev::kRodas3 && a.o.scheme != dev::kRos4) return hipErrorInvalidValue;
+  void* fn = persistent ? wide_fn<true>(a.o.scheme) : wide_fn<false>(a.o.scheme);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
   if (e != hipSuccess) return e;
   IntegrateArgs copy = a;
@@ -785,7 +802,7 @@ hipError_t launch_integrate_wide(bool persistent, int grid, const IntegrateArgs&
 }
 
 int integrate_wide_blocks_per_cu(bool persistent, size_t lds_bytes) {
-  void* fn = persistent ? wide_fn<true>() : wide_fn<false>();
+  void* fn = persistent ? wide_fn<true>(dev::kRodas3) : wide_fn<false>(dev::kRodas3);
   hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kT, lds_bytes) != hipSuccess) return 0;

@@ -22,6 +22,8 @@ struct MechArgs {
 struct OptsDev {
   double rtol, atol;
   int max_steps;
+  int scheme;                   // 0 Rodas3, 1 ROS4
+  int jac_fd;                   // 1: Jacobian by forward differences (n extra right-hand sides)
 };
 
 // Learned-cost logging (records written by the integration kernel).

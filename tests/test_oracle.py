@@ -735,3 +735,62 @@ def test_ros4_adaptive_closed_form_and_radau(mech_dir):
     assert np.all(np.abs(a[0][:, 0] - b[0][:, 0]) <= 10 * 1e-6 * b[0][:, 0])
     with pytest.raises(ValueError):
         T9.integrate(phi[:2], wl.dt, scheme=7)
+
+
+# ------------------------------------- forward-difference Jacobian (NEXT-3) ---
+# The integrator's FD mode stands for the conventional finite-difference
+# Jacobian that the paper's analytical one replaces (Introduction; Fig. 2).
+
+def test_jac_fd_isomer_closed_form(mech_dir):
+    """A <=> B isomers at constant T: f is linear in Y, so forward
+    differences reproduce the closed-form Jacobian (J_AA = -kf, J_AB = kr,
+    J_BA = kf, J_BB = -kr, no T coupling) up to rounding over the increment."""
+    kf, shift = 2.0e5, 0.7
+    M = O.Mech(_write(mechs.isomer_pair(kf, shift), mech_dir, "iso_fd"))
+    kr = kf / math.exp(shift)
+    # the second state's f is dominated by kr Y_B ~ 1e5, whose rounding over
+    # the 3e-11 increment of Y_A leaves ~1e-6 relative error in column A
+    for y, rel in ((np.array([1200.0, 0.9, 0.1]), 1e-7), (np.array([800.0, 1e-12, 1.0 - 1e-12]), 1e-5)):
+        J = M.jac_fd(1e5, y)
+        exact = np.array([[0.0, 0.0, 0.0], [0.0, -kf, kr], [0.0, kf, -kr]])
+        assert np.abs(J - exact).max() <= rel * kf, J
+
+
+@pytest.mark.parametrize("name", ["tiny9_1024", "spray54_262144"])
+def test_jac_fd_approximates_analytical(name, mech_dir):
+    """On real states the FD Jacobian approximates the analytical one in the
+    scaled form diag(1/s) J diag(s): on the 9-species cells every entry within
+    1e-5 of its row's largest, on the 54-species cells at least 99.5% of the
+    entries within 1e-4 of it. The rest are the columns of trace species
+    (Y ~ 1e-12) on cold cells, where the increment sqrt(u 1e-5) ~ 3e-11 is
+    far larger than Y and the quadratic terms of the rates spoil the forward
+    difference: the inaccuracy the analytical Jacobian removes."""
+    wl, mech, path, phi = synth.workload_inputs(name, mech_dir, n_cells=512)
+    M = O.Mech(path)
+    for c in synth.sample_indices(512, 8, 3):
+        y = np.concatenate([[phi[c, 0]], phi[c, 2:]])
+        Ja, Jf = M.jac(phi[c, 1], y), M.jac_fd(phi[c, 1], y)
+        s = np.maximum(np.abs(y), [1.0] + [1e-8] * (len(y) - 1))
+        A, B = Ja * s[None, :] / s[:, None], Jf * s[None, :] / s[:, None]
+        rowmax = np.abs(A).max(axis=1, keepdims=True)
+        r = np.where(rowmax > 0, np.abs(A - B) / np.where(rowmax > 0, rowmax, 1.0), 0.0)
+        if mech.n_species == 9:
+            assert r.max() <= 1e-5, c
+        else:
+            assert (r > 1e-4).mean() <= 5e-3 and np.percentile(r, 99) <= 1e-4, c
+
+
+def test_integration_fd_jacobian_matches_analytical(mech_dir):
+    """The integration with the FD Jacobian reaches the analytical run's
+    states within ten times the tolerance (both approximate the same exact
+    solution to it); an unknown Jacobian mode is rejected."""
+    wl, mech, path, phi = synth.workload_inputs("tiny9_1024", mech_dir, n_cells=128)
+    M = O.Mech(path)
+    a = M.integrate(phi, wl.dt, n_threads=4)
+    b = M.integrate(phi, wl.dt, n_threads=4, jacobian=O.JAC_FD)
+    assert (a[4] == 0).all() and (b[4] == 0).all()
+    tol = 1e-10 + 1e-6 * np.abs(a[0][:, 2:])
+    assert np.all(np.abs(b[0][:, 2:] - a[0][:, 2:]) <= 10 * tol)
+    assert np.all(np.abs(b[0][:, 0] - a[0][:, 0]) <= 10 * 1e-6 * a[0][:, 0])
+    with pytest.raises(ValueError):
+        M.integrate(phi[:2], wl.dt, jacobian=3)
