@@ -69,6 +69,15 @@ extern "C" {
 #define CHEM_JAC_ANALYTICAL 0
 #define CHEM_JAC_FD 1
 
+/* The integrated state (paper: Methodology, the Analytical Jacobian paragraph;
+ * pyJac's state vector omits the bath gas). CHEM_STATE_FULL: T and every Y,
+ * n = Ns + 1. CHEM_STATE_NO_BATH: the mechanism's last species is the bath
+ * gas; it is not integrated and its mass fraction is 1 - the sum of the
+ * others, n = Ns (needs Ns >= 2). The input's last mass fraction is then not
+ * read, and phi_out carries 1 - the sum of the others in it. */
+#define CHEM_STATE_FULL 0
+#define CHEM_STATE_NO_BATH 1
+
 /* Schedules. */
 #define CHEM_PLAIN 0              /* one launch per chemistry step, static cell-to-wave map */
 #define CHEM_PERSISTENT 1         /* resident waves pull cells from an atomic queue          */
@@ -89,6 +98,7 @@ typedef struct {
   int64_t hbm_budget_bytes; /* workspace budget for in-flight cells; 0 = 50% of free     */
   int32_t scheme;           /* CHEM_RODAS3 (default) or CHEM_ROS4                        */
   int32_t jacobian;         /* CHEM_JAC_ANALYTICAL (default) or CHEM_JAC_FD              */
+  int32_t state;            /* CHEM_STATE_FULL (default) or CHEM_STATE_NO_BATH           */
 } chem_opts;
 
 /* Fill o with the defaults above. Paper: Results and discussion (the Spray A

@@ -569,6 +569,97 @@ void orc_lu_solve(int n, const double* LU, const int* piv, double* b) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* The integrated state. Full: y = (T, Y_1..Y_Ns), n = Ns + 1. Bath gas      */
+/* dropped (pyJac's convention): the last species is not integrated, its     */
+/* mass fraction is 1 - sum of the others, y = (T, Y_1..Y_Ns-1), n = Ns.     */
+/* Its f is the full f without the last row; its Jacobian follows by the     */
+/* chain rule through Y_Ns = 1 - sum_j Y_j: column j of a species gets the   */
+/* full Jacobian's column j minus the last column.                           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  const orc_mech* m;
+  int red;               /* 1: bath gas (last species) dropped */
+  double *yfull, *ffull, *Jfull;
+} model_t;
+
+static void model_init(model_t* mo, const orc_mech* m, int red) {
+  int nf = m->ns + 1;
+  mo->m = m;
+  mo->red = red;
+  mo->yfull = (double*)calloc((size_t)nf * (nf + 2), sizeof(double));
+  mo->ffull = mo->yfull + nf;
+  mo->Jfull = mo->ffull + nf;
+}
+static void model_free(model_t* mo) { free(mo->yfull); }
+static int model_n(const model_t* mo) { return mo->m->ns + (mo->red ? 0 : 1); }
+
+/* Full state from the integrated one: Y_Ns = 1 - sum of the others, summed in
+ * ascending order. */
+static void model_full(const model_t* mo, const double* y, double* yf) {
+  int ns = mo->m->ns;
+  double sum = 0.0;
+  for (int i = 0; i < ns; ++i) yf[i] = y[i];
+  for (int i = 1; i < ns; ++i) sum = sum + y[i];
+  yf[ns] = 1.0 - sum;
+}
+
+static void model_rhs(model_t* mo, double p, const double* y, double* f) {
+  if (!mo->red) { orc_rhs(mo->m, p, y, f); return; }
+  int ns = mo->m->ns;
+  model_full(mo, y, mo->yfull);
+  orc_rhs(mo->m, p, mo->yfull, mo->ffull);
+  for (int i = 0; i < ns; ++i) f[i] = mo->ffull[i];
+}
+
+static void model_jac(model_t* mo, double p, const double* y, double* J) {
+  if (!mo->red) { orc_jac(mo->m, p, y, J); return; }
+  int ns = mo->m->ns, nf = ns + 1;
+  model_full(mo, y, mo->yfull);
+  orc_jac(mo->m, p, mo->yfull, mo->Jfull);
+  for (int i = 0; i < ns; ++i) {
+    J[(size_t)i * ns] = mo->Jfull[(size_t)i * nf];
+    for (int j = 1; j < ns; ++j) J[(size_t)i * ns + j] = mo->Jfull[(size_t)i * nf + j] - mo->Jfull[(size_t)i * nf + ns];
+  }
+}
+
+/* forward differences of the integrated f (same increment rule as orc_jac_fd) */
+static void model_jac_fd(model_t* mo, double p, const double* y, const double* f0, double* J) {
+  int n = model_n(mo);
+  double* yp = (double*)malloc(sizeof(double) * 2 * n);
+  double* fp = yp + n;
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) yp[i] = y[i];
+    double s = sqrt(FD_UROUND * fmax(1e-5, fabs(y[j])));
+    yp[j] = y[j] + s;
+    double d = yp[j] - y[j];
+    model_rhs(mo, p, yp, fp);
+    for (int i = 0; i < n; ++i) J[(size_t)i * n + j] = (fp[i] - f0[i]) / d;
+  }
+  free(yp);
+}
+
+int orc_state_rhs(const orc_mech* m, int state, double p, const double* y, double* f) {
+  if (!m || (state != ORC_STATE_FULL && state != ORC_STATE_NO_BATH) || (state == ORC_STATE_NO_BATH && m->ns < 2))
+    return -1;
+  model_t mo;
+  model_init(&mo, m, state == ORC_STATE_NO_BATH);
+  model_rhs(&mo, p, y, f);
+  model_free(&mo);
+  return 0;
+}
+
+int orc_state_jac(const orc_mech* m, int state, double p, const double* y, double* J) {
+  if (!m || (state != ORC_STATE_FULL && state != ORC_STATE_NO_BATH) || (state == ORC_STATE_NO_BATH && m->ns < 2))
+    return -1;
+  model_t mo;
+  model_init(&mo, m, state == ORC_STATE_NO_BATH);
+  model_jac(&mo, p, y, J);
+  model_free(&mo);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Rosenbrock methods in the transformed form: unknowns u_i, matrix          */
 /* M = I/(gamma h) - J, stage i solves                                       */
 /*   M u_i = f(y + sum_j a_ij u_j) + sum_j (c_ij / h) u_j,                   */
@@ -664,7 +755,7 @@ static int stage_f_source(const tableau_t* tb, int s) {
 
 /* One attempted step of size h from y, with f0 = f(y) and J = J(y) given.
  * Returns the LU status. */
-static int ros_attempt(const orc_mech* m, const tableau_t* tb, double p, const double* y, double h, work_t* w,
+static int ros_attempt(model_t* mo, const tableau_t* tb, double p, const double* y, double h, work_t* w,
                        double* y_new, double* err_vec) {
   int n = w->n;
   for (int i = 0; i < n; ++i)
@@ -680,7 +771,7 @@ static int ros_attempt(const orc_mech* m, const tableau_t* tb, double p, const d
         for (int j = 0; j < s; ++j) v = v + tb->a[s][j] * w->u[j * n + i];
         w->ys[i] = v;
       }
-      orc_rhs(m, p, w->ys, w->fs);
+      model_rhs(mo, p, w->ys, w->fs);
     } else if (src == 0) {
       for (int i = 0; i < n; ++i) w->fs[i] = w->f0[i];
     } /* src == 1: fs still holds stage s-1's f */
@@ -709,11 +800,14 @@ int orc_step(const orc_mech* m, int scheme, double p, const double* y, double h,
   const tableau_t* tb = tableau_of(scheme);
   if (!tb) return -1;
   work_t w;
+  model_t mo;
+  model_init(&mo, m, 0);
   work_alloc(&w, m->ns + 1);
   orc_rhs(m, p, y, w.f0);
   orc_jac(m, p, y, w.J);
-  int info = ros_attempt(m, tb, p, y, h, &w, y_new, err_vec);
+  int info = ros_attempt(&mo, tb, p, y, h, &w, y_new, err_vec);
   work_free(&w);
+  model_free(&mo);
   return info;
 }
 
@@ -732,10 +826,10 @@ int orc_rodas3_step(const orc_mech* m, double p, const double* y, double h, doub
 #define T_MAX 6000.0
 
 /* Adaptive integration of one cell over [0, dt]; y (length n) in/out. */
-static int integrate_cell(const orc_mech* m, double p, double dt, const orc_opts* o, double* y,
+static int integrate_cell(model_t* mo, double p, double dt, const orc_opts* o, double* y,
                           double* h_io, int* nacc_out, int* nrej_out, work_t* w, double* y_new,
                           double* err_vec) {
-  int n = m->ns + 1;
+  int n = model_n(mo);
   const tableau_t* tb = tableau_of(o->scheme);
   int nacc = 0, nrej = 0, attempts = 0, status = ORC_OK;
   for (int i = 0; i < n; ++i) if (!isfinite(y[i])) status = ORC_NONFINITE;
@@ -747,9 +841,9 @@ static int integrate_cell(const orc_mech* m, double p, double dt, const orc_opts
   while (status == ORC_OK && t < dt) {
     if (attempts >= o->max_steps) { status = ORC_MAX_STEPS; break; }
     if (need_start) {
-      orc_rhs(m, p, y, w->f0);
-      if (o->jacobian == ORC_JAC_FD) orc_jac_fd(m, p, y, w->f0, w->J);
-      else orc_jac(m, p, y, w->J);
+      model_rhs(mo, p, y, w->f0);
+      if (o->jacobian == ORC_JAC_FD) model_jac_fd(mo, p, y, w->f0, w->J);
+      else model_jac(mo, p, y, w->J);
       need_start = 0;
     }
     double rem = dt - t;
@@ -757,7 +851,7 @@ static int integrate_cell(const orc_mech* m, double p, double dt, const orc_opts
     int clipped = 0;
     if (hc >= rem) { hc = rem; clipped = 1; }
     if (hc < H_MIN) { status = ORC_H_UNDERFLOW; break; }
-    int info = ros_attempt(m, tb, p, y, hc, w, y_new, err_vec);
+    int info = ros_attempt(mo, tb, p, y, hc, w, y_new, err_vec);
     attempts++;
     if (info) { status = ORC_SINGULAR; break; }
     /* RMS error over all components */
@@ -824,11 +918,14 @@ typedef struct {
 
 static void* worker(void* arg) {
   job_t* jb = (job_t*)arg;
-  int ns = jb->m->ns, n = ns + 1, w2 = ns + 2;
+  int ns = jb->m->ns, w2 = ns + 2;
+  model_t mo;
+  model_init(&mo, jb->m, jb->o->state == ORC_STATE_NO_BATH);
+  int n = model_n(&mo);
   work_t w;
   work_alloc(&w, n);
-  double* y = (double*)malloc(sizeof(double) * n * 3);
-  double *y_new = y + n, *err = y + 2 * n;
+  double* y = (double*)malloc(sizeof(double) * (ns + 1) * 3);
+  double *y_new = y + ns + 1, *err = y + 2 * (ns + 1);
   for (;;) {
     long c = atomic_fetch_add(&jb->next, 1);
     if (c >= jb->n_cells) break;
@@ -838,7 +935,14 @@ static void* worker(void* arg) {
     for (int i = 0; i < ns; ++i) y[1 + i] = pin[2 + i];
     double h = jb->h_io ? jb->h_io[c] : 0.0;
     int na = 0, nr = 0;
-    int st = integrate_cell(jb->m, p, jb->dt, jb->o, y, &h, &na, &nr, &w, y_new, err);
+    /* without the bath gas, the input's last mass fraction is not read: it
+     * is 1 - the sum of the others, before and after the step */
+    int st = integrate_cell(&mo, p, jb->dt, jb->o, y, &h, &na, &nr, &w, y_new, err);
+    if (mo.red) {
+      double sum = 0.0;
+      for (int i = 1; i < ns; ++i) sum = sum + y[i];
+      y[ns] = 1.0 - sum;
+    }
     double* pout = jb->out + (size_t)c * w2;
     pout[0] = y[0];
     pout[1] = p;
@@ -850,6 +954,7 @@ static void* worker(void* arg) {
   }
   free(y);
   work_free(&w);
+  model_free(&mo);
   return NULL;
 }
 
@@ -857,7 +962,8 @@ int orc_integrate(const orc_mech* m, long n_cells, double dt, const orc_opts* o,
                   const double* phi_in, double* phi_out, double* h_io, int* n_acc, int* n_rej,
                   signed char* status, int n_threads) {
   if (!m || !o || n_cells < 0 || !(dt > 0.0) || (n_cells > 0 && (!phi_in || !phi_out)) || !tableau_of(o->scheme) ||
-      (o->jacobian != ORC_JAC_ANALYTICAL && o->jacobian != ORC_JAC_FD)) {
+      (o->jacobian != ORC_JAC_ANALYTICAL && o->jacobian != ORC_JAC_FD) ||
+      (o->state != ORC_STATE_FULL && o->state != ORC_STATE_NO_BATH) || (o->state == ORC_STATE_NO_BATH && m->ns < 2)) {
     snprintf(g_err, sizeof g_err, "orc_integrate: bad argument");
     return -1;
   }

@@ -39,7 +39,18 @@ typedef struct {
   int max_steps;    /* attempted steps per cell per call */
   int scheme;       /* ORC_RODAS3 (0) or ORC_ROS4 (1) */
   int jacobian;     /* ORC_JAC_ANALYTICAL (0) or ORC_JAC_FD (1) */
+  int state;        /* ORC_STATE_FULL (0) or ORC_STATE_NO_BATH (1) */
 } orc_opts;
+
+/* The integrated state: all species (n = Ns + 1), or, as pyJac does, without
+ * the bath gas, the mechanism's last species, whose mass fraction is then
+ * 1 - the sum of the others (n = Ns; needs Ns >= 2). */
+enum { ORC_STATE_FULL = 0, ORC_STATE_NO_BATH = 1 };
+
+/* Right-hand side and analytical Jacobian of the integrated state (n = Ns + 1
+ * or Ns entries, row-major n x n). Return 0, or -1 on a bad argument. */
+int orc_state_rhs(const orc_mech* m, int state, double p, const double* y, double* f);
+int orc_state_jac(const orc_mech* m, int state, double p, const double* y, double* J);
 
 /* How the integrator obtains J: analytically, or by forward differences
  * (the conventional way the paper's analytical Jacobian replaces). */

@@ -35,11 +35,12 @@ def build(verbose: bool = False) -> str:
 
 class _Opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("max_steps", ctypes.c_int),
-                ("scheme", ctypes.c_int), ("jacobian", ctypes.c_int)]
+                ("scheme", ctypes.c_int), ("jacobian", ctypes.c_int), ("state", ctypes.c_int)]
 
 
 RODAS3, ROS4 = 0, 1
 JAC_ANALYTICAL, JAC_FD = 0, 1
+STATE_FULL, STATE_NO_BATH = 0, 1
 
 
 _lib = None
@@ -61,6 +62,8 @@ def lib():
         L.orc_rhs.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, _dp]
         L.orc_jac.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, _dp]
         L.orc_jac_fd.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, _dp, _dp]
+        L.orc_state_rhs.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _dp, _dp]
+        L.orc_state_jac.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _dp, _dp]
         L.orc_lu.argtypes = [ctypes.c_int, _dp, _ip]
         L.orc_lu_solve.argtypes = [ctypes.c_int, _dp, _ip, _dp]
         L.orc_rodas3_tableau.argtypes = [_dp, _dp, _dp, _dp, _dp]
@@ -141,6 +144,22 @@ class Mech:
         lib().orc_jac_fd(self._h, float(p), _d(y), _d(f0), _d(J))
         return J
 
+    def state_rhs(self, p: float, y, state: int):
+        """f of the integrated state (full, or without the bath gas)."""
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        f = np.zeros(len(y))
+        if lib().orc_state_rhs(self._h, int(state), float(p), _d(y), _d(f)) != 0:
+            raise ValueError("bad state")
+        return f
+
+    def state_jac(self, p: float, y, state: int):
+        """Analytical Jacobian of the integrated state."""
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        J = np.zeros((len(y), len(y)))
+        if lib().orc_state_jac(self._h, int(state), float(p), _d(y), _d(J)) != 0:
+            raise ValueError("bad state")
+        return J
+
     def rodas3_step(self, p: float, y, h: float):
         y = np.ascontiguousarray(y, dtype=np.float64)
         yn, e = np.zeros(self.n), np.zeros(self.n)
@@ -161,7 +180,8 @@ class Mech:
         return yn, e
 
     def integrate(self, phi, dt: float, rtol=1e-6, atol=1e-10, max_steps=100000, h_io=None,
-                  n_threads: int = 1, scheme: int = RODAS3, jacobian: int = JAC_ANALYTICAL):
+                  n_threads: int = 1, scheme: int = RODAS3, jacobian: int = JAC_ANALYTICAL,
+                  state: int = STATE_FULL):
         phi = np.ascontiguousarray(phi, dtype=np.float64)
         n_cells = phi.shape[0]
         assert phi.shape[1] == self.ns + 2
@@ -170,7 +190,7 @@ class Mech:
         na = np.zeros(n_cells, dtype=np.int32)
         nr = np.zeros(n_cells, dtype=np.int32)
         st = np.zeros(n_cells, dtype=np.int8)
-        o = _Opts(rtol, atol, max_steps, scheme, jacobian)
+        o = _Opts(rtol, atol, max_steps, scheme, jacobian, state)
         rc = lib().orc_integrate(self._h, n_cells, float(dt), ctypes.byref(o), _d(phi), _d(out), _d(h),
                                  _i(na), _i(nr), st.ctypes.data_as(ctypes.POINTER(ctypes.c_byte)),
                                  int(n_threads))

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libchem.so")
 PLAIN, PERSISTENT, PERSISTENT_BINNED = 0, 1, 2
 RODAS3, ROS4 = 0, 1
 JAC_ANALYTICAL, JAC_FD = 0, 1
+STATE_FULL, STATE_NO_BATH = 0, 1
 CELL_OK, CELL_MAX_STEPS, CELL_H_UNDERFLOW, CELL_NONFINITE, CELL_SINGULAR, CELL_T_RANGE = range(6)
 
 _ERRORS = {-1: "CHEM_EINVAL", -2: "CHEM_EMECH", -3: "CHEM_EHIP", -4: "CHEM_ENOMEM", -5: "CHEM_ESTATE",
@@ -36,7 +37,7 @@ class Opts(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("cells_per_wave", ctypes.c_int32),
                 ("queue_chunk", ctypes.c_int32), ("blocks", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
-                ("scheme", ctypes.c_int32), ("jacobian", ctypes.c_int32)]
+                ("scheme", ctypes.c_int32), ("jacobian", ctypes.c_int32), ("state", ctypes.c_int32)]
 
 
 class TrainOpts(ctypes.Structure):

@@ -235,6 +235,7 @@ static int check_opts(const chem_opts* o) {
   if (o->scheme != CHEM_RODAS3 && o->scheme != CHEM_ROS4) return fail(CHEM_EINVAL, "unknown scheme");
   if (o->jacobian != CHEM_JAC_ANALYTICAL && o->jacobian != CHEM_JAC_FD)
     return fail(CHEM_EINVAL, "unknown jacobian mode");
+  if (o->state != CHEM_STATE_FULL && o->state != CHEM_STATE_NO_BATH) return fail(CHEM_EINVAL, "unknown state");
   return CHEM_OK;
 }
 
@@ -485,6 +486,8 @@ int launch_step(chem_solver* s, const chem_opts& o, int64_t n, double dt, const 
   a.o.max_steps = o.max_steps;
   a.o.scheme = o.scheme;
   a.o.jac_fd = o.jacobian == CHEM_JAC_FD;
+  a.o.no_bath = o.state == CHEM_STATE_NO_BATH;
+  if (a.o.no_bath && s->ns < 2) return fail(CHEM_EINVAL, "dropping the bath gas needs at least two species");
   a.dt = dt;
   a.n = n;
   a.phi_in = in;

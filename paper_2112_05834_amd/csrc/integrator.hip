@@ -56,6 +56,20 @@ constexpr int kXor1 = 0xB1;        // quad_perm [1,0,3,2]
 constexpr int kXor2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int kHalfMirror = 0x141; // lane i <-> 7-i within 8
 constexpr int kMirror = 0x140;     // lane i <-> 15-i within 16
+constexpr int kRowBcast15 = 0x142; // lane 15 of each row into the next row
+constexpr int kRowBcast31 = 0x143; // lane 31 into rows 2 and 3
+
+// DPP move into the rows of ROWMASK only; the other rows keep old
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_rows_d(double old, double v) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_rows_i(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWMASK, 0xf, false);
+}
 
 template <int G>
 struct Grp {
@@ -81,16 +95,19 @@ struct Grp {
   }
   // Sum over the 64 virtual lanes of a cell (lanes beyond the group add +0)
   // with one pairing tree for every G: xor 1, xor 2, then the 8-lane and
-  // 16-lane mirrors inside a DPP row, then rows (0+1) + (2+3).
+  // 16-lane mirrors inside a DPP row, then rows (0+1) + (2+3). With one cell
+  // per wave the rows are combined by DPP row broadcasts: row 3 ends with
+  // (r3 + r2) + (r1 + r0), the same value as (r0 + r1) + (r2 + r3) in every
+  // bit (IEEE addition commutes), read from lane 63.
   __device__ static __forceinline__ double sum(double x) {
     x = x + dpp_d<kXor1>(x);
     x = x + dpp_d<kXor2>(x);
     x = x + dpp_d<kHalfMirror>(x);
     x = x + dpp_d<kMirror>(x);
     if constexpr (G == 64) {
-      const double r0 = readlane_d(x, 0), r1 = readlane_d(x, 16);
-      const double r2 = readlane_d(x, 32), r3 = readlane_d(x, 48);
-      return (r0 + r1) + (r2 + r3);
+      x = x + dpp_rows_d<kRowBcast15, 0xA>(0.0, x);   // rows 1, 3: + row 0, row 2
+      x = x + dpp_rows_d<kRowBcast31, 0xC>(0.0, x);   // rows 2, 3: + row 1
+      return readlane_d(x, 63);
     } else if constexpr (G == 32) {
       return (x + __shfl_xor(x, 16, 64)) + (0.0 + 0.0);
     } else {
@@ -103,7 +120,9 @@ struct Grp {
     x = fmax(x, dpp_d<kHalfMirror>(x));
     x = fmax(x, dpp_d<kMirror>(x));
     if constexpr (G == 64) {
-      return fmax(fmax(readlane_d(x, 0), readlane_d(x, 16)), fmax(readlane_d(x, 32), readlane_d(x, 48)));
+      x = fmax(x, dpp_rows_d<kRowBcast15, 0xA>(x, x));
+      x = fmax(x, dpp_rows_d<kRowBcast31, 0xC>(x, x));
+      return readlane_d(x, 63);
     } else if constexpr (G == 32) {
       return fmax(x, __shfl_xor(x, 16, 64));
     } else {
@@ -116,8 +135,9 @@ struct Grp {
     x = ::min(x, dpp_i<kHalfMirror>(x));
     x = ::min(x, dpp_i<kMirror>(x));
     if constexpr (G == 64) {
-      return ::min(::min(__builtin_amdgcn_readlane(x, 0), __builtin_amdgcn_readlane(x, 16)),
-                   ::min(__builtin_amdgcn_readlane(x, 32), __builtin_amdgcn_readlane(x, 48)));
+      x = ::min(x, dpp_rows_i<kRowBcast15, 0xA>(x, x));
+      x = ::min(x, dpp_rows_i<kRowBcast31, 0xC>(x, x));
+      return __builtin_amdgcn_readlane(x, 63);
     } else if constexpr (G == 32) {
       return ::min(x, __shfl_xor(x, 16, 64));
     } else {
@@ -495,12 +515,46 @@ struct Cell {
     return f;
   }
 
+  // Without the bath gas (the last species, lane ns) its mass fraction is
+  // 1 - the sum of the other species: this lane's value, with lane ns
+  // replaced by that.
+  __device__ static __forceinline__ double with_bath(int ns, double v) {
+    const int i = Gp::gl();
+    const double s = Gp::sum((i >= 1 && i < ns) ? v : 0.0);
+    return i == ns ? 1.0 - s : v;
+  }
+
+  // The Jacobian of the state without the bath gas, from the full one in
+  // ca.J: by the chain rule through Y_bath = 1 - sum_j Y_j every species
+  // column loses the bath column. The bath's row and column are cleared, so
+  // that its row of M is g e_ns, decoupled from the others.
+  __device__ static __forceinline__ void reduce_bath(const CellArea& ca, int ns) {
+    const int i = Gp::gl();
+    wsync();
+    if (i < ns) {
+      double* Jr = ca.J + i * NN;
+      const double jb = Jr[ns];
+#pragma unroll
+      for (int j = 1; j < NN; ++j)
+        if (j < ns) Jr[j] = Jr[j] - jb;
+      Jr[ns] = 0.0;
+    } else if (i == ns) {
+#pragma unroll
+      for (int j = 0; j < NN; ++j) ca.J[i * NN + j] = 0.0;
+    }
+    wsync();
+  }
+
   // Jacobian by forward differences, written row-major into ca.J: one more
-  // right-hand side per state component (f0 = f(y) given). Every lane holds
-  // its component of the perturbed state; lane j adds the increment.
+  // right-hand side per integrated component (f0 = f(y) given). Every lane
+  // holds its component of the perturbed state; lane j adds the increment.
+  // Without the bath gas the perturbed state's bath lane is derived again,
+  // so the columns are those of the reduced system, and the bath's row stays
+  // zero.
   __device__ static void fd_jacobian(const MechArgs& A, const MechLds& L, const CellArea& ca, double p, double y,
-                                     double f0) {
-    const int n = A.ns + 1;
+                                     double f0, bool nb) {
+    const int ns = A.ns;
+    const int n = nb ? ns : ns + 1;
     const int i = Gp::gl();
     if (i < NN) {
 #pragma unroll
@@ -511,8 +565,10 @@ struct Cell {
       const double yj = Gp::bcast(y, j);
       const double yp = yj + fd_increment(yj);
       const double d = yp - yj;
-      const double fj = rhs<false>(A, L, ca, p, i == j ? yp : y);
-      if (i < NN) ca.J[i * NN + j] = (fj - f0) / d;
+      double ypert = i == j ? yp : y;
+      if (nb) ypert = with_bath(ns, ypert);
+      const double fj = rhs<false>(A, L, ca, p, ypert);
+      if (i < NN && !(nb && i == ns)) ca.J[i * NN + j] = (fj - f0) / d;
     }
     wsync();
   }
@@ -620,15 +676,20 @@ struct Cell {
   // adaptive Rosenbrock integration (scheme SCHEME) over [0, dt] for one cell
   // (y: this lane's component)
   // -------------------------------------------------------------------------
-  template <int SCHEME>
+  // GEN: honour the forward-difference Jacobian and the state without the
+  // bath gas (run-time options); without it both are compiled out, so that
+  // the kernels of the default options carry none of their code.
+  template <int SCHEME, bool GEN>
   __device__ static __forceinline__ void integrate(const MechArgs& A, const MechLds& L, const CellArea& ca,
                                                    const OptsDev& o, double p, double dt, double& y,
                                                    double& hio, int& nacc_o, int& nrej_o, int& status_o) {
     using TB = Tab<SCHEME>;
     const int ns = A.ns;
-    const int n = ns + 1;
+    const bool nb = GEN && o.no_bath != 0;   // bath gas (lane ns) derived, not integrated
+    const int n = nb ? ns : ns + 1;       // integrated components
     const int i = Gp::gl();
-    const bool valid = i <= ns;
+    const bool valid = i < n;
+    if (nb) y = with_bath(ns, y);
     double M[NN];
     int pos;
     double rdiag;
@@ -646,11 +707,12 @@ struct Cell {
         break;
       }
       if (need) {
-        if (o.jac_fd) {
+        if (GEN && o.jac_fd) {
           f0 = rhs<false>(A, L, ca, p, y);
-          fd_jacobian(A, L, ca, p, y, f0);
+          fd_jacobian(A, L, ca, p, y, f0, nb);
         } else {
           f0 = rhs<true>(A, L, ca, p, y);
+          if (nb) reduce_bath(ca, ns);
         }
         need = false;
       }
@@ -692,6 +754,7 @@ struct Cell {
           if (st > 0) ys = ys + tab_a<SCHEME>(st, 0) * u1;
           if (st > 1) ys = ys + tab_a<SCHEME>(st, 1) * u2;
           if (st > 2) ys = ys + tab_a<SCHEME>(st, 2) * u3;
+          if (nb) ys = with_bath(ns, ys);
           fs = rhs<false>(A, L, ca, p, ys);
         } else if (src == kFy) {
           fs = f0;
@@ -700,6 +763,7 @@ struct Cell {
         if (st > 0) v = v + (tab_c<SCHEME>(st, 0) / hc) * u1;
         if (st > 1) v = v + (tab_c<SCHEME>(st, 1) / hc) * u2;
         if (st > 2) v = v + (tab_c<SCHEME>(st, 2) / hc) * u3;
+        if (nb && i == ns) v = 0.0;         // the bath lane takes no step of its own
         const double x = solve(M, pos, rdiag, v);
         if (st == 0) u1 = x;
         else if (st == 1) u2 = x;
@@ -711,6 +775,7 @@ struct Cell {
       yn = yn + TB::m[1] * u2;
       yn = yn + TB::m[2] * u3;
       yn = yn + TB::m[3] * u4;
+      if (nb) yn = with_bath(ns, yn);
       double ev = 0.0 + TB::e[0] * u1;
       ev = ev + TB::e[1] * u2;
       ev = ev + TB::e[2] * u3;
@@ -774,7 +839,7 @@ __device__ __forceinline__ void cell_features(int ns, double y, double p, double
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-template <int NN, int G, int SCHEME>
+template <int NN, int G, int SCHEME, bool GEN>
 __device__ __forceinline__ void run_cell(const IntegrateArgs& a, const MechLds& L, const CellArea& ca,
                                          long long cell) {
   using C = Cell<NN, G>;
@@ -788,7 +853,7 @@ __device__ __forceinline__ void run_cell(const IntegrateArgs& a, const MechLds& 
   if (a.log.cap > 0) cell_features<G>(ns, y, p, a.dt, ft);
   double h = a.h_io ? a.h_io[cell] : 0.0;
   int nacc, nrej, st;
-  C::template integrate<SCHEME>(a.m, L, ca, a.o, p, a.dt, y, h, nacc, nrej, st);
+  C::template integrate<SCHEME, GEN>(a.m, L, ca, a.o, p, a.dt, y, h, nacc, nrej, st);
   double* pout = a.phi_out + cell * w2;
   if (i == 0) {
     pout[0] = y;
@@ -823,7 +888,7 @@ __device__ __forceinline__ void run_cell(const IntegrateArgs& a, const MechLds& 
 template <int NN>
 constexpr int max_waves_per_eu() { return NN >= 32 ? 1 : 2; }
 
-template <int NN, int G, bool PERSIST, int SCHEME>
+template <int NN, int G, bool PERSIST, int SCHEME, bool GEN>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, max_waves_per_eu<NN>())))
 k_integrate(IntegrateArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -837,7 +902,7 @@ k_integrate(IntegrateArgs a) {
   const CellArea ca = cell_area<NN>(base, a.m.nr, a.m.ns);
   if (!PERSIST) {
     const long long cell = (static_cast<long long>(blockIdx.x) * a.wpb + wave) * CPW + grp;
-    if (cell < a.n) run_cell<NN, G, SCHEME>(a, L, ca, cell);
+    if (cell < a.n) run_cell<NN, G, SCHEME, GEN>(a, L, ca, cell);
   } else {
     for (;;) {
       unsigned long long idx = 0;
@@ -847,7 +912,7 @@ k_integrate(IntegrateArgs a) {
       const long long end = min(static_cast<long long>(idx) + a.chunk, a.n);
       for (long long q = static_cast<long long>(idx); q < end; ++q) {
         const long long cell = a.perm ? static_cast<long long>(a.perm[q]) : q;
-        run_cell<NN, G, SCHEME>(a, L, ca, cell);
+        run_cell<NN, G, SCHEME, GEN>(a, L, ca, cell);
       }
     }
   }
@@ -957,15 +1022,19 @@ int variants_for(int n, Variant* out, int max_out) {
 int cell_doubles(int nn, int nr, int ns) { return cell_doubles_c(nn, nr, ns); }
 
 template <int NN, int G, bool P>
-static void* integrate_fn(int scheme) {
-  return scheme == dev::kRos4 ? reinterpret_cast<void*>(&k_integrate<NN, G, P, dev::kRos4>)
-                              : reinterpret_cast<void*>(&k_integrate<NN, G, P, dev::kRodas3>);
+static void* integrate_fn(int scheme, bool gen) {
+  if (gen)
+    return scheme == dev::kRos4 ? reinterpret_cast<void*>(&k_integrate<NN, G, P, dev::kRos4, true>)
+                                : reinterpret_cast<void*>(&k_integrate<NN, G, P, dev::kRodas3, true>);
+  return scheme == dev::kRos4 ? reinterpret_cast<void*>(&k_integrate<NN, G, P, dev::kRos4, false>)
+                              : reinterpret_cast<void*>(&k_integrate<NN, G, P, dev::kRodas3, false>);
 }
 
-static void* find_integrate(const Variant& v, bool persistent, int scheme) {
+static void* find_integrate(const Variant& v, bool persistent, int scheme, bool gen) {
   if (scheme != dev::kRodas3 && scheme != dev::kRos4) return nullptr;
 #define V(a, b)                                                                                        \
-  if (v.nn == a && v.g == b) return persistent ? integrate_fn<a, b, true>(scheme) : integrate_fn<a, b, false>(scheme);
+  if (v.nn == a && v.g == b)                                                                           \
+    return persistent ? integrate_fn<a, b, true>(scheme, gen) : integrate_fn<a, b, false>(scheme, gen);
   CHEM_VARIANTS(V)
 #undef V
   return nullptr;
@@ -973,7 +1042,7 @@ static void* find_integrate(const Variant& v, bool persistent, int scheme) {
 
 hipError_t launch_integrate(const Variant& v, bool persistent, int grid, const IntegrateArgs& a,
                             size_t lds_bytes, hipStream_t st) {
-  void* fn = find_integrate(v, persistent, a.o.scheme);
+  void* fn = find_integrate(v, persistent, a.o.scheme, a.o.jac_fd || a.o.no_bath);
   if (!fn) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
   if (e != hipSuccess) return e;
@@ -984,7 +1053,7 @@ hipError_t launch_integrate(const Variant& v, bool persistent, int grid, const I
 }
 
 int integrate_blocks_per_cu(const Variant& v, bool persistent, int wpb, size_t lds_bytes) {
-  void* fn = find_integrate(v, persistent, dev::kRodas3);
+  void* fn = find_integrate(v, persistent, dev::kRodas3, false);
   if (!fn) return 0;
   hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
   int nb = 0;

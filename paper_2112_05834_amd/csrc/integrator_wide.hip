@@ -501,17 +501,48 @@ __device__ void solve_w(const double* M, int n, int ld, const Wide& W, const dou
   }
 }
 
+// ---- the state without the bath gas ----------------------------------------------
+// The bath gas is the last species (component ns): its mass fraction is 1 -
+// the sum of the other species (a workgroup sum in a fixed order).
+__device__ void with_bath_w(double* vec, int ns, double* red) {
+  const int t = threadIdx.x;
+  const double s = bsum((t >= 1 && t < ns) ? vec[t] : 0.0, red);
+  if (t == ns) vec[ns] = 1.0 - s;
+  __syncthreads();
+}
+
+// Jacobian of the state without the bath gas from the full one (column-major
+// in HBM): by the chain rule every species column loses the bath column; the
+// bath's row and column are cleared, so its row of M is g e_ns.
+__device__ void reduce_bath_w(double* J, int ns, int ld) {
+  const int t = threadIdx.x;
+  if (t < ns) {
+    const double jb = J[ns * ld + t];
+    for (int j = 1; j < ns; ++j) J[j * ld + t] = J[j * ld + t] - jb;
+    J[ns * ld + t] = 0.0;
+  } else if (t == ns) {
+    for (int j = 0; j <= ns; ++j) J[j * ld + ns] = 0.0;
+  }
+  __syncthreads();
+}
+
 // ---- adaptive Rosenbrock integration (scheme SCHEME) over [0, dt] for one cell
 // (state in W.y) ---------------------------------------------------------------
-template <int SCHEME>
+// GEN: honour the forward-difference Jacobian and the state without the bath
+// gas; without it both are compiled out.
+template <int SCHEME, bool GEN>
 __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, double* J, double* M, int ld,
                             const OptsDev& o, double p, double dt, double& hio, int& nacc_o, int& nrej_o,
                             int& status_o) {
   using TB = Tab<SCHEME>;
-  const int n = A.ns + 1;
+  const int ns = A.ns;
+  const int n = ns + 1;                 // size of J and M
+  const bool nb = GEN && o.no_bath != 0;   // bath gas (component ns) derived, not integrated
+  const int ni = nb ? ns : n;           // integrated components
   const int t = threadIdx.x;
   int status = 0;
-  const bool bad = (t < n && !isfinite(W.y[t])) || !isfinite(p) || !(p > 0.0);
+  if (nb) with_bath_w(W.y, ns, W.red);
+  const bool bad = (t < ni && !isfinite(W.y[t])) || !isfinite(p) || !(p > 0.0);
   if (__syncthreads_or(bad)) status = 3;
   double h = hio > 0.0 ? hio : dt;
   double hnext = h, tt = 0.0;
@@ -523,22 +554,27 @@ __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, 
       break;
     }
     if (need) {
-      if (o.jac_fd) {
+      if (GEN && o.jac_fd) {
         rhs_w<false>(A, L, W, p, W.y, W.f0, nullptr, ld);
         // forward differences: column j from f(y + d_j e_j), the perturbed
-        // state staged in W.ys and its f in W.fs
-        for (int j = 0; j < n; ++j) {
+        // state staged in W.ys and its f in W.fs; without the bath gas the
+        // perturbed state's bath component is derived again, and the bath's
+        // column and row stay zero
+        if (nb && t < n) J[ns * ld + t] = 0.0;
+        for (int j = 0; j < ni; ++j) {
           const double yj = W.y[j];
           const double yp = yj + fd_increment(yj);
           const double d = yp - yj;
           if (t < n) W.ys[t] = t == j ? yp : W.y[t];
           __syncthreads();
+          if (nb) with_bath_w(W.ys, ns, W.red);
           rhs_w<false>(A, L, W, p, W.ys, W.fs, nullptr, ld);
-          if (t < n) J[j * ld + t] = (W.fs[t] - W.f0[t]) / d;
+          if (t < n) J[j * ld + t] = (nb && t == ns) ? 0.0 : (W.fs[t] - W.f0[t]) / d;
           __syncthreads();
         }
       } else {
         rhs_w<true>(A, L, W, p, W.y, W.f0, J, ld);
+        if (nb) reduce_bath_w(J, ns, ld);
       }
       need = false;
     }
@@ -584,12 +620,13 @@ __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, 
           W.ys[t] = ys;
         }
         __syncthreads();
+        if (nb) with_bath_w(W.ys, ns, W.red);
         rhs_w<false>(A, L, W, p, W.ys, W.fs, nullptr, ld);
       }
       if (t < n) {
         double v = src == kFy ? W.f0[t] : W.fs[t];
         for (int j = 0; j < st; ++j) v = v + (TB::c[st][j] / hc) * W.u[j][t];
-        W.v[t] = v;
+        W.v[t] = (nb && t == ns) ? 0.0 : v;   // the bath takes no step of its own
       }
       __syncthreads();
       solve_w(M, n, ld, W, W.v, W.u[st]);
@@ -606,9 +643,10 @@ __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, 
       q = ev / sc;
       W.yn[t] = yn;
     }
-    const double acc = bsum(t < n ? q * q : 0.0, W.red);
-    double err = sqrt(acc / n);
-    const bool nonfinite = __syncthreads_or(t < n && !isfinite(yn));
+    if (nb) with_bath_w(W.yn, ns, W.red);
+    const double acc = bsum(t < ni ? q * q : 0.0, W.red);
+    double err = sqrt(acc / ni);
+    const bool nonfinite = __syncthreads_or(t < ni && !isfinite(yn));
     double hnew;
     if (nonfinite || !isfinite(err)) {
       err = INFINITY;
@@ -647,7 +685,7 @@ __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, 
   status_o = status;
 }
 
-template <int SCHEME>
+template <int SCHEME, bool GEN>
 __device__ void run_cell_w(const IntegrateArgs& a, const MechLds& L, const Wide& W, double* J, double* M,
                            long long cell) {
   const int ns = a.m.ns, n = ns + 1, w2 = ns + 2;
@@ -667,7 +705,7 @@ __device__ void run_cell_w(const IntegrateArgs& a, const MechLds& L, const Wide&
   }
   double h = a.h_io ? a.h_io[cell] : 0.0;
   int nacc, nrej, st;
-  integrate_w<SCHEME>(a.m, L, W, J, M, a.ld, a.o, p, a.dt, h, nacc, nrej, st);
+  integrate_w<SCHEME, GEN>(a.m, L, W, J, M, a.ld, a.o, p, a.dt, h, nacc, nrej, st);
   double* pout = a.phi_out + cell * w2;
   if (t < n) pout[t == 0 ? 0 : 1 + t] = W.y[t];
   if (t == 0) {
@@ -694,7 +732,7 @@ __device__ void run_cell_w(const IntegrateArgs& a, const MechLds& L, const Wide&
 // ---- kernels ---------------------------------------------------------------------
 // Each workgroup owns workspace slot blockIdx.x. Plain: cells blockIdx.x,
 // blockIdx.x + gridDim.x, ... (static); persistent: chunks from the queue.
-template <bool PERSIST, int SCHEME>
+template <bool PERSIST, int SCHEME, bool GEN>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_integrate_wide(IntegrateArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   stage_mech(smem, a.m);
@@ -703,7 +741,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
   double* J = a.ws + static_cast<long long>(blockIdx.x) * a.ws_stride;
   double* M = J + static_cast<long long>(a.m.ns + 1) * a.ld;
   if (!PERSIST) {
-    for (long long cell = blockIdx.x; cell < a.n; cell += gridDim.x) run_cell_w<SCHEME>(a, L, W, J, M, cell);
+    for (long long cell = blockIdx.x; cell < a.n; cell += gridDim.x) run_cell_w<SCHEME, GEN>(a, L, W, J, M, cell);
   } else {
     for (;;) {
       if (threadIdx.x == 0) W.qslot[0] = atomicAdd(a.head, static_cast<unsigned long long>(a.chunk));
@@ -714,7 +752,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
       const long long end = min(static_cast<long long>(idx) + a.chunk, a.n);
       for (long long q = static_cast<long long>(idx); q < end; ++q) {
         const long long cell = a.perm ? static_cast<long long>(a.perm[q]) : q;
-        run_cell_w<SCHEME>(a, L, W, J, M, cell);
+        run_cell_w<SCHEME, GEN>(a, L, W, J, M, cell);
       }
     }
   }
@@ -785,15 +823,19 @@ __global__ void __launch_bounds__(256) k_lu_wide(LuArgs a) {
 int wide_cell_bytes(int ns, int nr, int ld) { return static_cast<int>(sizeof(double)) * wide_doubles(ns, nr, ld); }
 
 template <bool P>
-static void* wide_fn(int scheme) {
-  return scheme == dev::kRos4 ? reinterpret_cast<void*>(&k_integrate_wide<P, dev::kRos4>)
-                              : reinterpret_cast<void*>(&k_integrate_wide<P, dev::kRodas3>);
+static void* wide_fn(int scheme, bool gen) {
+  if (gen)
+    return scheme == dev::kRos4 ? reinterpret_cast<void*>(&k_integrate_wide<P, dev::kRos4, true>)
+                                : reinterpret_cast<void*>(&k_integrate_wide<P, dev::kRodas3, true>);
+  return scheme == dev::kRos4 ? reinterpret_cast<void*>(&k_integrate_wide<P, dev::kRos4, false>)
+                              : reinterpret_cast<void*>(&k_integrate_wide<P, dev::kRodas3, false>);
 }
 
 hipError_t launch_integrate_wide(bool persistent, int grid, const IntegrateArgs& a, size_t lds_bytes,
                                  hipStream_t st) {
   if (a.o.scheme != dev::kRodas3 && a.o.scheme != dev::kRos4) return hipErrorInvalidValue;
-  void* fn = persistent ? wide_fn<true>(a.o.scheme) : wide_fn<false>(a.o.scheme);
+  const bool gen = a.o.jac_fd || a.o.no_bath;
+  void* fn = persistent ? wide_fn<true>(a.o.scheme, gen) : wide_fn<false>(a.o.scheme, gen);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
   if (e != hipSuccess) return e;
   IntegrateArgs copy = a;
@@ -802,7 +844,7 @@ hipError_t launch_integrate_wide(bool persistent, int grid, const IntegrateArgs&
 }
 
 int integrate_wide_blocks_per_cu(bool persistent, size_t lds_bytes) {
-  void* fn = persistent ? wide_fn<true>(dev::kRodas3) : wide_fn<false>(dev::kRodas3);
+  void* fn = persistent ? wide_fn<true>(dev::kRodas3, false) : wide_fn<false>(dev::kRodas3, false);
   hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kT, lds_bytes) != hipSuccess) return 0;

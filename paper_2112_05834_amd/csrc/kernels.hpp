@@ -24,6 +24,7 @@ struct OptsDev {
   int max_steps;
   int scheme;                   // 0 Rodas3, 1 ROS4
   int jac_fd;                   // 1: Jacobian by forward differences (n extra right-hand sides)
+  int no_bath;                  // 1: the last species (bath gas) is not integrated: Y = 1 - sum of the others
 };
 
 // Learned-cost logging (records written by the integration kernel).

@@ -55,15 +55,26 @@ def _compare(phi0, gpu, ref, counts_gpu, counts_ref, what):
 CASES = [("tiny9_1024", 1024, None), ("spray54_262144", 262144, 256), ("large160_524288", 48, None)]
 
 
+VARIANTS = {
+    "ros4": (dict(scheme=chem.ROS4), dict(scheme=O.ROS4)),
+    "fd": (dict(jacobian=chem.JAC_FD), dict(jacobian=O.JAC_FD)),
+    "nobath": (dict(state=chem.STATE_NO_BATH), dict(state=O.STATE_NO_BATH)),
+    "ros4_fd_nobath": (dict(scheme=chem.ROS4, jacobian=chem.JAC_FD, state=chem.STATE_NO_BATH),
+                       dict(scheme=O.ROS4, jacobian=O.JAC_FD, state=O.STATE_NO_BATH)),
+}
+
+
 @pytest.mark.parametrize("name,n_gpu,n_check", CASES)
-@pytest.mark.parametrize("variant", ["ros4", "fd"])
+@pytest.mark.parametrize("variant", ["ros4", "fd", "nobath", "ros4_fd_nobath"])
 def test_variant_matches_oracle(tmp_path, name, n_gpu, n_check, variant):
+    """ros4: Shampine's scheme; fd: forward-difference Jacobian; nobath: the
+    last species (the bath gas) not integrated, its mass fraction 1 - the
+    sum of the others (n = Ns); and the three together."""
+    if variant == "ros4_fd_nobath" and name != "tiny9_1024":
+        pytest.skip("the combination runs on the 9-species cells only")
     wl, mech, path, phi = synth.workload_inputs(name, str(tmp_path), n_cells=n_gpu)
-    if variant == "ros4":
-        kw, okw = dict(scheme=chem.ROS4), dict(scheme=O.ROS4)
-    else:
-        kw, okw = dict(jacobian=chem.JAC_FD), dict(jacobian=O.JAC_FD)
-    if variant == "fd" and name == "spray54_262144":
+    kw, okw = VARIANTS[variant]
+    if "fd" in variant and name == "spray54_262144":
         n_check = 128
     S = chem.Solver(chem.Mechanism(path), chem.default_opts(schedule=chem.PERSISTENT, **kw), device=0)
     r = S.integrate(_to(phi), wl.dt)
@@ -74,6 +85,9 @@ def test_variant_matches_oracle(tmp_path, name, n_gpu, n_check, variant):
     assert np.array_equal(gst, st)
     _compare(phi[idx], r.phi.cpu().numpy()[idx], ref, (r.n_acc.cpu().numpy()[idx], r.n_rej.cpu().numpy()[idx]),
              (na, nr), "%s %s" % (variant, name))
+    if "nobath" in variant:
+        out = r.phi.cpu().numpy()
+        assert np.abs(out[:, 2:].sum(axis=1) - 1.0).max() <= 1e-15
     # plain and persistent schedules give the same bits for the variant too
     if name != "spray54_262144":
         S.set_opts(chem.default_opts(schedule=chem.PLAIN, **kw))

@@ -794,3 +794,80 @@ def test_integration_fd_jacobian_matches_analytical(mech_dir):
     assert np.all(np.abs(b[0][:, 0] - a[0][:, 0]) <= 10 * 1e-6 * a[0][:, 0])
     with pytest.raises(ValueError):
         M.integrate(phi[:2], wl.dt, jacobian=3)
+
+
+# ------------------------------------------ bath gas dropped (NEXT-4) ---
+# pyJac's state convention: the last species (the bath gas) is not
+# integrated; its mass fraction is 1 - the sum of the others, n = Ns.
+
+def test_no_bath_isomer_closed_form(mech_dir):
+    """A <=> B with B the bath gas: y = (T, Y_A), f_A = -(kf + kr) Y_A + kr
+    because Y_B = 1 - Y_A, so the reduced Jacobian is [[0, 0], [0, -(kf +
+    kr)]]; the integration relaxes Y_A to equilibrium as the exponential."""
+    kf, shift = 2.0e5, 0.7
+    M = O.Mech(_write(mechs.isomer_pair(kf, shift), mech_dir, "iso_nb"))
+    kr = kf / math.exp(shift)
+    y = np.array([1200.0, 0.9])
+    f = M.state_rhs(1e5, y, O.STATE_NO_BATH)
+    J = M.state_jac(1e5, y, O.STATE_NO_BATH)
+    assert abs(f[1] - (-(kf + kr) * 0.9 + kr)) <= 1e-12 * kf
+    assert abs(f[0]) <= 1e-9 * kf
+    assert np.abs(J - np.array([[0.0, 0.0], [0.0, -(kf + kr)]])).max() <= 1e-9 * kf
+    yeq = kr / (kf + kr)
+    phi = np.array([[1100.0, 1e5, 0.95, 0.05], [900.0, 1e5, 0.0, 1.0]])
+    for dt in [1e-6, 1e-5, 1e-4]:
+        out, h, na, nr, st = M.integrate(phi, dt, state=O.STATE_NO_BATH)
+        assert (st == 0).all()
+        ya = yeq + (phi[:, 2] - yeq) * math.exp(-(kf + kr) * dt)
+        assert np.all(np.abs(out[:, 2] - ya) <= 10 * (1e-10 + 1e-6 * np.abs(ya)))
+        assert np.all(out[:, 3] == 1.0 - out[:, 2])
+
+
+@pytest.mark.parametrize("name", ["tiny9_1024", "spray54_262144"])
+def test_no_bath_jacobian_vs_finite_differences(name, mech_dir):
+    """The reduced Jacobian (the full one's columns minus its last column, by
+    the chain rule through Y_Ns = 1 - sum Y_j) against central differences of
+    the reduced right-hand side itself, in the scaled form of R22."""
+    wl, mech, path, phi = synth.workload_inputs(name, mech_dir, n_cells=512)
+    M = O.Mech(path)
+    for c in synth.sample_indices(512, 8, 5):
+        y = np.concatenate([[phi[c, 0]], phi[c, 2:-1]])      # without the last species
+        p = phi[c, 1]
+        n = len(y)
+        s = np.abs(y).copy()
+        s[0] = max(s[0], 1.0)
+        s[1:] = np.maximum(s[1:], 1e-8)
+        J = M.state_jac(p, y, O.STATE_NO_BATH)
+        Jfd = np.zeros_like(J)
+        for j in range(n):
+            d = 1e-6 * s[j]
+            yp, ym = y.copy(), y.copy()
+            yp[j] += d
+            ym[j] -= d
+            Jfd[:, j] = (M.state_rhs(p, yp, O.STATE_NO_BATH) - M.state_rhs(p, ym, O.STATE_NO_BATH)) / (2 * d)
+        Ja = J * s[None, :] / s[:, None]
+        Jf = Jfd * s[None, :] / s[:, None]
+        rowmax = np.abs(Ja).max(axis=1, keepdims=True)
+        assert not (np.abs(Ja - Jf) > 1e-6 * np.abs(Jf) + 1e-9 * rowmax).any(), c
+
+
+def test_no_bath_integration_matches_full_state(mech_dir):
+    """Dropping the bath gas integrates the same ODE: the states agree with
+    the full-state integration within ten times the tolerance, the mass
+    fractions sum to one to rounding, and the input's last mass fraction is
+    not read."""
+    wl, mech, path, phi = synth.workload_inputs("tiny9_1024", mech_dir, n_cells=128)
+    M = O.Mech(path)
+    a = M.integrate(phi, wl.dt, n_threads=4)
+    b = M.integrate(phi, wl.dt, n_threads=4, state=O.STATE_NO_BATH)
+    assert (a[4] == 0).all() and (b[4] == 0).all()
+    tol = 1e-10 + 1e-6 * np.abs(a[0][:, 2:])
+    assert np.all(np.abs(b[0][:, 2:] - a[0][:, 2:]) <= 10 * tol)
+    assert np.all(np.abs(b[0][:, 0] - a[0][:, 0]) <= 10 * 1e-6 * a[0][:, 0])
+    assert np.abs(b[0][:, 2:].sum(axis=1) - 1.0).max() <= 4e-16
+    junk = phi.copy()
+    junk[:, -1] = 123.0
+    c = M.integrate(junk, wl.dt, n_threads=4, state=O.STATE_NO_BATH)
+    assert np.array_equal(c[0], b[0]) and np.array_equal(c[2], b[2])
+    with pytest.raises(ValueError):
+        M.integrate(phi[:2], wl.dt, state=2)
