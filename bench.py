@@ -58,19 +58,32 @@ def bytes_per_launch_wide(n, n_acc, n_rej, cells):
     return 64.0 * n * n * att + 24.0 * n * n * starts + 2.0 * 8 * (n + 1) * cells
 
 
-def measured_traffic(kernel_src):
+def _sources_current(text, sources):
+    """True if the summary names a sha256 prefix for every kernel source and
+    each matches the file as it is now."""
+    for src in sources:
+        m = re.search(re.escape(src) + r" sha256 prefix ([0-9a-f]+)", text)
+        full = os.path.join(ROOT, "paper_2112_05834_amd", "csrc", src)
+        if not m or not hashlib.sha256(open(full, "rb").read()).hexdigest().startswith(m.group(1)):
+            return False
+    return True
+
+
+# sources the wave-per-cell integration kernel is compiled from
+WAVE_KERNEL_SOURCES = ("integrator.hip", "device_common.hpp")
+
+
+def measured_traffic():
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source (else None)."""
+    taken on the current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", "k_integrate_spray54_262144_hbm_counters.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(r"sha256 prefix ([0-9a-f]+)", text)
     t = re.search(r"total ([0-9.]+) MB\.", text)
-    if not m or not t:
+    if not t or not _sources_current(text, WAVE_KERNEL_SOURCES):
         return None
-    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    return float(t.group(1)) * 1e6 if h.startswith(m.group(1)) else None
+    return float(t.group(1)) * 1e6
 
 
 def measured_wide_traffic():
@@ -82,30 +95,23 @@ def measured_wide_traffic():
         return None
     text = open(path).read()
     t = re.search(r"total ([0-9.]+) TB\.", text)
-    if not t:
+    if not t or not _sources_current(text, ("integrator_wide.hip", "device_common.hpp")):
         return None
-    for src in ("integrator_wide.hip", "device_common.hpp"):
-        m = re.search(re.escape(src) + r" sha256 prefix ([0-9a-f]+)", text)
-        full = os.path.join(ROOT, "paper_2112_05834_amd", "csrc", src)
-        if not m or not hashlib.sha256(open(full, "rb").read()).hexdigest().startswith(m.group(1)):
-            return None
     return float(t.group(1)) * 1e12
 
 
-def measured_fp64_ops(kernel_src):
+def measured_fp64_ops():
     """Executed FP64 operations per launch (all lanes) from the committed FP64
-    instruction-counter summary, if it was taken on the current kernel source
+    instruction-counter summary, if it was taken on the current kernel sources
     (else None)."""
     path = os.path.join(ROOT, "profiles", "k_integrate_spray54_262144_fp64_counters.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(r"sha256 prefix ([0-9a-f]+)", text)
     t = re.search(r"executed FP64 operations: ([0-9.e+]+) per launch", text)
-    if not m or not t:
+    if not t or not _sources_current(text, WAVE_KERNEL_SOURCES):
         return None
-    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    return float(t.group(1)) if h.startswith(m.group(1)) else None
+    return float(t.group(1))
 
 
 # integration tolerances of every solver the benchmark configures
@@ -453,9 +459,8 @@ def main():
     else:
         kern_s = float(np.mean(R["kms"])) / 1e3 if len(R["kms"]) else float(np.mean(R["ms"])) / 1e3
         achieved = flops / kern_s
-    src = os.path.join(ROOT, "paper_2112_05834_amd", "csrc", "integrator.hip")
-    traffic = measured_traffic(src)
-    executed = measured_fp64_ops(src)
+    traffic = measured_traffic()
+    executed = measured_fp64_ops()
     if (args.workload != "spray54_262144" or args.chain > 1 or args.cells > 0 or
             (args.rtol, args.atol) != (1e-6, 1e-10)):
         traffic = None

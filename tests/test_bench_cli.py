@@ -29,11 +29,20 @@ def test_flop_and_byte_models():
     assert b == 64.0 * 161 * 161 * 4 + 24.0 * 161 * 161 * 3 + 2 * 8 * 162 * 2
 
 
-def test_traffic_only_for_the_profiled_source(tmp_path):
+def test_counters_only_for_the_profiled_sources():
+    import hashlib
     import bench
-    src = os.path.join(ROOT, "paper_2112_05834_amd", "csrc", "integrator.hip")
-    t = bench.measured_traffic(src)
+    t = bench.measured_traffic()
     assert t is None or t > 2.3e8          # at least phi in and out of 262144 cells
-    other = tmp_path / "k.hip"
-    other.write_text("changed\n")
-    assert bench.measured_traffic(str(other)) is None
+    e = bench.measured_fp64_ops()
+    assert e is None or e > 1e12
+    srcs = bench.WAVE_KERNEL_SOURCES
+    cur = {s: hashlib.sha256(open(os.path.join(ROOT, "paper_2112_05834_amd", "csrc", s), "rb")
+                             .read()).hexdigest()[:16] for s in srcs}
+    text = "; ".join("%s sha256 prefix %s" % (s, cur[s]) for s in srcs)
+    assert bench._sources_current(text, srcs)
+    # a stale prefix for either source, or a missing one, makes the figures unusable
+    for s in srcs:
+        stale = text.replace(cur[s], "0" * 16)
+        assert not bench._sources_current(stale, srcs)
+    assert not bench._sources_current(text.split("; ")[0], srcs)
