@@ -9,14 +9,15 @@
 // bounded by the HBM budget. Everything else of the cell (state, stage
 // vectors, concentrations, per-reaction rates) lives in LDS.
 //
-// The LU is a right-looking blocked getrf: a panel of 12 columns is factored
-// in LDS with partial pivoting (first index of the largest |a|), its row
-// interchanges are applied to the other columns, the 12-row block of U is
-// solved against the unit-lower diagonal block, and the trailing matrix
-// receives the rank-12 update in one pass through HBM. Every element sees
-// the same sequence of operations as in an unblocked row-swapping LU, in the
-// same order, so the factors do not depend on the blocking.
-#include <hip/hip_runtime.h>
+// The LU is a left-looking blocked getrf that never moves a row in HBM:
+// the row interchanges are kept as a permutation, so physical row q of M
+// stays at offset q of every column. Panel by panel (12 columns), the panel
+// is first brought up to date with every finished column to its left, each
+// wave holding three of its columns in registers while the finished columns
+// stream through LDS twelve at a time; wave 0 then factors the panel in
+// registers and writes it back. Every element sees the same sequence of
+// operations as in an unblocked row-swapping LU, in the same order, so the
+// factors do not depend on the blocking.
 
 #include <cmath>
 #include <cstdint>
@@ -33,19 +34,21 @@ using namespace dev;
 constexpr int kT = kWideThreads;
 constexpr int kNB = kWidePanel;
 
-// Per-cell LDS area. Region A (right-hand-side buffers) and region B (LU
-// panel and U block) are never live at the same time and share storage; so
-// do the stage input ys and the solve right-hand side v, and the stage
-// derivative fs and the trial state yn.
+// Per-cell LDS area. Region A (right-hand-side buffers) and region B (two
+// 12-column buffers of the LU) are never live at the same time and share
+// storage; so do the stage input ys and the solve right-hand side v, and the
+// stage derivative fs and the trial state yn.
 struct Wide {
   double *C, *gRT, *hRT, *RB;                   // A: ns, ns, ns, 5 nr
   double *panel, *U12;                          // B: kNB ld, kNB ld
   double *y, *f0, *fs, *ys, *yn, *v, *u[4];     // 8 distinct vectors of ld
   double* red;                                  // 16
-  int* piv;                                     // ld
-  int* perm;                                    // ld
-  int* sig;                                     // ld: source row of each row in one panel
+  double* ub;                                   // 144: per wave, 12 x 3 values of the LU's U block
+  int* piv;                                     // ld: getrf's interchange at each step
+  int* perm;                                    // ld: physical row of each logical row
+  int* pos;                                     // ld: logical row of each physical row (-1 beyond n)
   int* ired;                                    // 16
+  int* zpm;                                     // 32: zero-pivot columns, one 12-bit mask per panel
   unsigned long long* qslot;                    // 1
 };
 
@@ -55,10 +58,10 @@ __host__ __device__ inline int wide_region(int ns, int nr, int ld) {
   return ((a > b ? a : b) + 1) & ~1;
 }
 
-// doubles: region, 8 vectors, reduction scratch; ints: piv, perm, sig, ired;
-// one 64-bit queue slot
+// doubles: region, 8 vectors, reduction scratch, U block; ints: piv, perm,
+// pos, ired, zpm; one 64-bit queue slot
 __host__ __device__ inline int wide_doubles(int ns, int nr, int ld) {
-  return wide_region(ns, nr, ld) + 8 * ld + 16 + (3 * ld + 16) / 2 + 2;
+  return wide_region(ns, nr, ld) + 8 * ld + 16 + 144 + (3 * ld + 48) / 2 + 2;
 }
 
 __device__ inline Wide wide_area(double* base, int ns, int nr, int ld) {
@@ -78,12 +81,14 @@ __device__ inline Wide wide_area(double* base, int ns, int nr, int ld) {
   W.ys = W.v;
   for (int k = 0; k < 4; ++k) W.u[k] = q + (4 + k) * ld;
   W.red = q + 8 * ld;
-  int* ip = reinterpret_cast<int*>(W.red + 16);
+  W.ub = W.red + 16;
+  int* ip = reinterpret_cast<int*>(W.ub + 144);
   W.piv = ip;
   W.perm = ip + ld;
-  W.sig = ip + 2 * ld;
+  W.pos = ip + 2 * ld;
   W.ired = ip + 3 * ld;
-  W.qslot = reinterpret_cast<unsigned long long*>(ip + 3 * ld + 16);
+  W.zpm = ip + 3 * ld + 16;
+  W.qslot = reinterpret_cast<unsigned long long*>(ip + 3 * ld + 48);
   return W;
 }
 
@@ -103,7 +108,7 @@ __device__ __forceinline__ double bsum(double v, double* red) {
 // element (i, j) at J[j * ld + i]. Thread t owns state component t (0 = T,
 // t = 1..Ns species t-1) and, for the Jacobian, row t.
 template <bool JAC>
-__device__ void rhs_w(const MechArgs& A, const MechLds& L, const Wide& W, double p, const double* yv, double* fout,
+__device__ __forceinline__ void rhs_w(const MechArgs& A, const MechLds& L, const Wide& W, double p, const double* yv, double* fout,
                       double* J, int ld) {
   const int ns = A.ns, nr = A.nr, n = ns + 1;
   const int t = threadIdx.x;
@@ -260,223 +265,502 @@ __device__ void rhs_w(const MechArgs& A, const MechLds& L, const Wide& W, double
   __syncthreads();
 }
 
-// ---- blocked LU with partial pivoting ---------------------------------------------
-// M: n x n column-major (leading dimension ld) in HBM, overwritten by L (unit
-// lower, below the diagonal) and U. W.piv[k] = row interchanged with row k
-// at step k, W.perm = the resulting row order. Returns the first zero pivot
-// column + 1 (0 if none); such a column is left unreduced, as getrf does.
-// The panel is factored by wave 0 alone (no workgroup barrier per column);
-// the whole workgroup applies its interchanges, solves the U block and
-// updates the trailing matrix.
-__device__ int lu_w(double* M, int n, int ld, const Wide& W) {
-  const int t = threadIdx.x;
-  if (t < ld) W.perm[t] = t;
-  int info = 0;
-  for (int k0 = 0; k0 < n; k0 += kNB) {
-    const int nb = min(kNB, n - k0);
-    if (t < ld) {
-      const bool in = t >= k0 && t < n;
-      for (int c = 0; c < nb; ++c) W.panel[c * ld + t] = in ? M[(k0 + c) * ld + t] : 0.0;
-      W.sig[t] = t;
-    }
-    __syncthreads();
-    if (t < 64) {
-      for (int c = 0; c < nb; ++c) {
-        const int k = k0 + c;
-        double* pc = W.panel + c * ld;
-        // first index of the largest |a| among rows k..n-1 (a NaN on the
-        // diagonal stays the pivot; elsewhere it never wins)
-        double key = -1.0;
-        int idx = 1 << 30;
-        for (int r = k + t; r < n; r += 64) {
-          const double av = fabs(pc[r]);
-          const double kv = (av != av) ? (r == k ? INFINITY : -1.0) : av;
-          if (kv > key) {
-            key = kv;
-            idx = r;
-          }
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-          const double ok = __shfl_xor(key, off);
-          const int oi = __shfl_xor(idx, off);
-          if (ok > key || (ok == key && oi < idx)) {
-            key = ok;
-            idx = oi;
-          }
-        }
-        const int pv = idx;
-        if (t == 0) {
-          W.piv[k] = pv;
-          const int tmp = W.perm[k];
-          W.perm[k] = W.perm[pv];
-          W.perm[pv] = tmp;
-          const int tms = W.sig[k];
-          W.sig[k] = W.sig[pv];
-          W.sig[pv] = tms;
-        }
-        if (pv != k && t < nb) {
-          double* q = W.panel + t * ld;
-          const double tmp = q[k];
-          q[k] = q[pv];
-          q[pv] = tmp;
-        }
-        wsync();
-        const double akk = pc[k];
-        if (akk == 0.0) {
-          if (!info) info = k + 1;
-          continue;
-        }
-        for (int r = k + 1 + t; r < n; r += 64) {
-          const double l = pc[r] / akk;
-          pc[r] = l;
-          for (int c2 = c + 1; c2 < nb; ++c2) {
-            double* q = W.panel + c2 * ld;
-            q[r] = q[r] - l * q[k];
-          }
-        }
-        wsync();
-      }
-      if (t == 0) W.ired[15] = info;
-    }
-    __syncthreads();
-    info = W.ired[15];
-    // panel back to HBM, and its interchanges on the other columns
-    if (t < ld && t >= k0 && t < n)
-      for (int c = 0; c < nb; ++c) M[(k0 + c) * ld + t] = W.panel[c * ld + t];
-    // The panel's interchanges compose to row i <- row sig[i]; only rows
-    // k0..k0+nb-1 and their pivot rows can move. All sources are read before
-    // any destination is written.
-    for (int j = t; j < n; j += kT) {
-      if (j >= k0 && j < k0 + nb) continue;
-      double* col = M + j * ld;
-      double va[kNB], vb[kNB];
-#pragma unroll
-      for (int c = 0; c < kNB; ++c) {
-        const int ia = k0 + c, ib = c < nb ? W.piv[k0 + c] : ia;
-        va[c] = (c < nb && W.sig[ia] != ia) ? col[W.sig[ia]] : 0.0;
-        vb[c] = (c < nb && W.sig[ib] != ib) ? col[W.sig[ib]] : 0.0;
-      }
-#pragma unroll
-      for (int c = 0; c < kNB; ++c) {
-        const int ia = k0 + c, ib = c < nb ? W.piv[k0 + c] : ia;
-        if (c < nb && W.sig[ia] != ia) col[ia] = va[c];
-        if (c < nb && W.sig[ib] != ib) col[ib] = vb[c];
-      }
-    }
-    __syncthreads();
-    const int j0 = k0 + nb, m = n - j0;
-    if (m > 0) {
-      // U block: L11^-1 A12, one column per thread
-      for (int j = j0 + t; j < n; j += kT) {
-        double* col = M + j * ld;
-        double x[kNB];
-#pragma unroll
-        for (int q = 0; q < kNB; ++q) x[q] = q < nb ? col[k0 + q] : 0.0;
-#pragma unroll
-        for (int q = 1; q < kNB; ++q) {
-#pragma unroll
-          for (int q2 = 0; q2 < q; ++q2)
-            if (q < nb) x[q] = x[q] - W.panel[q2 * ld + k0 + q] * x[q2];
-        }
-#pragma unroll
-        for (int q = 0; q < kNB; ++q) {
-          if (q < nb) {
-            col[k0 + q] = x[q];
-            W.U12[(j - j0) * kNB + q] = x[q];
-          }
-        }
-      }
-      __syncthreads();
-      // trailing update A22 -= L21 U12: threads 0..127 and 128..255 take
-      // alternate columns; consecutive threads take consecutive rows
-      const int half = t >> 7, rl = t & 127;
-      for (int rb = rl; rb < m; rb += 128) {
-        const int r = j0 + rb;
-        double lr[kNB];
-#pragma unroll
-        for (int q = 0; q < kNB; ++q) lr[q] = q < nb ? W.panel[q * ld + r] : 0.0;
-        // eight columns per round: loads first, then the updates, then stores
-        for (int jb = half; jb < m; jb += 16) {
-          double av[8];
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const int jj = jb + 2 * i;
-            av[i] = jj < m ? M[(j0 + jj) * ld + r] : 0.0;
-          }
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const int jj = jb + 2 * i;
-            if (jj < m) {
-              const double* u = W.U12 + jj * kNB;
-#pragma unroll
-              for (int q = 0; q < kNB; ++q)
-                if (q < nb) av[i] = av[i] - lr[q] * u[q];
-              M[(j0 + jj) * ld + r] = av[i];
-            }
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  return info;
+// The per-cell area is LDS; pointers into it are generic in the Wide struct.
+// Converted to the LDS address space, accesses compile to LDS instructions
+// (not flat ones, whose completion is counted together with global loads)
+// even where the compiler cannot trace them to the shared array.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(3))) T* lds(T* p) {
+  return (__attribute__((address_space(3))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(3))) T* lds(const T* p) {
+  return (const __attribute__((address_space(3))) T*)p;
+}
+// a pair of doubles as a native vector (128-bit LDS and global accesses)
+typedef double dv2 __attribute__((ext_vector_type(2)));
+// the same for the workspace slot in HBM (global loads and stores)
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* glb(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* glb(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
 }
 
-// x = M^-1 b with the factors of lu_w (b, x: LDS vectors, distinct).
-// Forward substitution in blocks of kSB columns (each element receives its
-// terms in ascending column order), then backward in blocks from the
-// bottom. Wave 0 solves the diagonal triangle with the block's factors
-// loaded up front; every thread then updates its row with kSB independent
-// loads in flight.
+// ---- wave-wide primitives (all 64 lanes active) ---------------------------------
+__device__ __forceinline__ double rl_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+// every pattern reads a lane inside the same DPP row
+template <int CTRL>
+__device__ __forceinline__ double dppd(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ int dppi(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
+}
+// into the rows of ROWMASK only (the others keep old)
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_rows(double old, double v) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_rows_i(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWMASK, 0xf, false);
+}
+// xor 1, xor 2, the 8- and 16-lane mirrors inside a row, then rows 1 and 3
+// take lane 15 of the row below and rows 2 and 3 lane 31: lane 63 ends with
+// the result
+__device__ __forceinline__ double wave_max(double x) {
+  x = fmax(x, dppd<0xB1>(x));
+  x = fmax(x, dppd<0x4E>(x));
+  x = fmax(x, dppd<0x141>(x));
+  x = fmax(x, dppd<0x140>(x));
+  x = fmax(x, dpp_rows<0x142, 0xA>(x, x));
+  x = fmax(x, dpp_rows<0x143, 0xC>(x, x));
+  return rl_d(x, 63);
+}
+__device__ __forceinline__ int wave_min(int x) {
+  x = ::min(x, dppi<0xB1>(x));
+  x = ::min(x, dppi<0x4E>(x));
+  x = ::min(x, dppi<0x141>(x));
+  x = ::min(x, dppi<0x140>(x));
+  x = ::min(x, dpp_rows_i<0x142, 0xA>(x, x));
+  x = ::min(x, dpp_rows_i<0x143, 0xC>(x, x));
+  return __builtin_amdgcn_readlane(x, 63);
+}
+
+// an int kept in a double-sized LDS slot (low word), and back
+__device__ __forceinline__ double int_in_double(int v) { return __hiloint2double(0, v); }
+__device__ __forceinline__ int int_of_double(double d) { return __double2loint(d); }
+
+// ---- blocked LU with partial pivoting ---------------------------------------------
+// M: n x n column-major (leading dimension ld) in HBM, overwritten by L (unit
+// lower) and U. No row is moved: logical row i of the factors is physical row
+// W.perm[i] (offset perm[i] in every column), W.pos is the inverse (-1 beyond
+// n), and W.piv[k] is the logical row interchanged with row k at step k
+// (getrf's ipiv, from 0). Returns the first zero pivot column + 1 (0 if none);
+// such a column is left unreduced and its multipliers are not applied, as
+// getrf does.
+//
+// Register layout: lane l of a wave holds physical rows l + 64 s, s < kRS.
+// Panel p (columns k0 .. k0 + nb - 1) is first updated with every finished
+// column k < k0, twelve at a time: wave w owns panel columns 3w .. 3w + 2, and
+// the twelve finished columns of block b arrive in LDS as rows of twelve
+// multipliers (loaded from HBM while the previous block is applied). For
+// block b (columns kb .. kb + 11) the twelve rows at logical kb .. kb + 11
+// first solve their unit lower triangle (36 lanes, one per row and column,
+// the solved value broadcast along each 16-lane row by DPP); every row below
+// then subtracts the twelve multiplier-times-U terms in ascending k. The panel
+// then goes through LDS to wave 0, which factors it column by column (pivot
+// search by DPP reductions, no barrier) and writes it back.
+constexpr int kRS = 4;              // row slots per lane: n <= 256
+constexpr int kCW = kNB / 4;        // panel columns per wave in the update
+constexpr int kPre = 6;             // two-double loads per thread for one 12-column block (ld <= 256)
+static_assert(kT == 256 && kNB == 12, "four waves of three panel columns each");
+
+__device__ __forceinline__ void block_load(const double* src, int cnt2, dv2 (&r)[kPre]) {
+  const auto* s = glb(reinterpret_cast<const dv2*>(src));
+#pragma unroll
+  for (int i = 0; i < kPre; ++i) {
+    const int e = static_cast<int>(threadIdx.x) + kT * i;
+    r[i] = dv2{0.0, 0.0};
+    if (e < cnt2) r[i] = s[e];
+  }
+}
+// the block (column-major, kNB columns of ld) into LDS as rows of kNB:
+// element (row q, column m) at dst[q * kNB + m]
+__device__ __forceinline__ void block_store_t(double* dst, int ld, int cnt2, const dv2 (&r)[kPre]) {
+  auto* d = lds(dst);
+#pragma unroll
+  for (int i = 0; i < kPre; ++i) {
+    const int e = static_cast<int>(threadIdx.x) + kT * i;
+    if (e < cnt2) {
+      const int m = (2 * e) / ld, q = 2 * e - m * ld;   // q even, q + 1 < ld
+      d[q * kNB + m] = r[i].x;
+      d[(q + 1) * kNB + m] = r[i].y;
+    }
+  }
+}
+
+// apply f(row array, slot) to each of the four per-slot arrays by name (an
+// array indexed [s][c] with s known only at run time would go to scratch)
+template <int C, class F>
+__device__ __forceinline__ void each_slot(double (&r0)[C], double (&r1)[C], double (&r2)[C], double (&r3)[C],
+                                          F&& f) {
+  f(r0, 0);
+  f(r1, 1);
+  f(r2, 2);
+  f(r3, 3);
+}
+
+// this wave's panel columns (k0 + 3w + cc) from M, rows beyond n and columns
+// beyond the panel as zero
+__device__ __forceinline__ void load_cols(double (&a0)[kCW], double (&a1)[kCW], double (&a2)[kCW],
+                                          double (&a3)[kCW], const double* Mg, int n, int ld, int k0, int nb) {
+  const auto* M = glb(Mg);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  each_slot(a0, a1, a2, a3, [&](double (&row)[kCW], const int s) {
+    const int q = lane + 64 * s;
+#pragma unroll
+    for (int cc = 0; cc < kCW; ++cc) {
+      const int c = kCW * w + cc;
+      row[cc] = (q < n && c < nb) ? M[(k0 + c) * ld + q] : 0.0;
+    }
+  });
+}
+
+// one 64-bit value of lane SRC of each 16-lane row, to every lane of that row
+template <int SRC>
+__device__ __forceinline__ double row_share_c(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + SRC, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + SRC, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+// the same with src a constant after unrolling
+__device__ __forceinline__ double row_share(double v, int src) {
+  switch (src) {
+    case 0: return row_share_c<0>(v);
+    case 1: return row_share_c<1>(v);
+    case 2: return row_share_c<2>(v);
+    case 3: return row_share_c<3>(v);
+    case 4: return row_share_c<4>(v);
+    case 5: return row_share_c<5>(v);
+    case 6: return row_share_c<6>(v);
+    case 7: return row_share_c<7>(v);
+    case 8: return row_share_c<8>(v);
+    case 9: return row_share_c<9>(v);
+    default: return row_share_c<10>(v);
+  }
+}
+
+// Apply finished block b (its rows of multipliers in Lt, LDS) to this wave's
+// panel columns. zm: the block's zero-pivot columns (skipped).
+__device__ __forceinline__ void apply_block(double (&A0)[kCW], double (&A1)[kCW], double (&A2)[kCW],
+                                            double (&A3)[kCW], const int (&ps)[kRS], const double* Ltg, int kb,
+                                            int zm, const Wide& W) {
+  using LD = __attribute__((address_space(3))) double;
+  using LD2 = __attribute__((address_space(3))) dv2;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const LD* Lt = lds(Ltg);
+  LD* T = lds(W.ub) + 36 * w;   // this wave's 12 x 3 table
+  // the block's own rows (logical kb .. kb + 11) into the table
+  each_slot(A0, A1, A2, A3, [&](double (&row)[kCW], const int s) {
+    const int m = ps[s] - kb;
+    if (m >= 0 && m < kNB) {
+#pragma unroll
+      for (int cc = 0; cc < kCW; ++cc) T[m * kCW + cc] = row[cc];
+    }
+  });
+  wsync();
+  // their unit lower triangle: lane 16 cc + m holds row m, column cc
+  const int cc = lane >> 4, m = lane & 15;
+  const bool act = cc < kCW && m < kNB;
+  double x = act ? T[m * kCW + cc] : 0.0;
+  double lr[kNB];
+  {
+    const int q = act ? lds(W.perm)[kb + m] : 0;
+    const LD2* r = reinterpret_cast<const LD2*>(Lt + q * kNB);
+#pragma unroll
+    for (int j = 0; j < kNB / 2; ++j) {
+      const dv2 v = r[j];
+      lr[2 * j] = v.x;
+      lr[2 * j + 1] = v.y;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j + 1 < kNB; ++j) {
+    if (((zm >> j) & 1) == 0) {
+      const double u = row_share(x, j);
+      const double y = x - lr[j] * u;
+      x = m > j ? y : x;
+    }
+  }
+  if (act) T[m * kCW + cc] = x;
+  wsync();
+  // every row below the block: twelve terms in ascending k; the block's own
+  // rows take their solved values
+  double U[kNB][kCW];
+#pragma unroll
+  for (int j = 0; j < kNB; ++j)
+#pragma unroll
+    for (int c = 0; c < kCW; ++c) U[j][c] = T[j * kCW + c];
+  each_slot(A0, A1, A2, A3, [&](double (&row)[kCW], const int s) {
+    const int q = lane + 64 * s;
+    const int rel = ps[s] - kb;
+    if (rel >= kNB) {
+      const LD2* r = reinterpret_cast<const LD2*>(Lt + q * kNB);
+      double l[kNB];
+#pragma unroll
+      for (int j = 0; j < kNB / 2; ++j) {
+        const dv2 v = r[j];
+        l[2 * j] = v.x;
+        l[2 * j + 1] = v.y;
+      }
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) {
+        if (((zm >> j) & 1) == 0) {
+#pragma unroll
+          for (int c = 0; c < kCW; ++c) row[c] = row[c] - l[j] * U[j][c];
+        }
+      }
+    } else if (rel >= 0) {
+#pragma unroll
+      for (int c = 0; c < kCW; ++c) row[c] = T[rel * kCW + c];
+    }
+  });
+}
+
+// All four waves: factor panel columns k0 .. k0 + nb - 1. The panel arrives in
+// LDS as rows of kNB doubles (H[q * kNB + c], physical row q); lane l of wave
+// w holds row q = 64 w + l in registers for the whole panel. At each column
+// every wave finds its best candidate (DPP reductions) and that row's lane
+// writes the candidate's key, code and remaining entries to the wave's LDS
+// slot (two sets, by column parity); after one barrier every lane picks the
+// same winner from the four slots, reads its row (a broadcast) and updates its
+// own row. Writes the panel to M and the positions to W.pos / W.perm.
+constexpr int kCand = 2 + kNB;   // per wave and parity: key, code, row entries
+
+__device__ __forceinline__ void factor_panel(double* Mg, const double* Hg, int n, int ld, int k0, int nb,
+                                             const Wide& W) {
+  using LD = __attribute__((address_space(3))) double;
+  using LD2 = __attribute__((address_space(3))) dv2;
+  const LD* H = lds(Hg);
+  LD* cand = lds(W.ub);   // 2 x 4 x kCand doubles (the U-block tables are idle here)
+  auto* M = glb(Mg);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int q = t;        // this lane's physical row
+  int pq = q < n ? lds(W.pos)[q] : -1;
+  int info = lds(W.ired)[15];
+  double P[kNB];
+  {
+    const LD2* r = reinterpret_cast<const LD2*>(H + (q < n ? q : 0) * kNB);
+#pragma unroll
+    for (int j = 0; j < kNB / 2; ++j) {
+      const dv2 v = r[j];
+      P[2 * j] = q < n ? v.x : 0.0;
+      P[2 * j + 1] = q < n ? v.y : 0.0;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kNB; ++c) {
+    if (c < nb) {
+      const int k = k0 + c;
+      // first logical row of the largest |a| among rows k..n-1 (a NaN on the
+      // diagonal stays the pivot; elsewhere it never wins); code = logical
+      // position * 256 + physical row
+      const double av = fabs(P[c]);
+      const double key = pq < k ? -1.0 : (av != av ? (pq == k ? INFINITY : -1.0) : av);
+      const int code = pq * 256 + q;
+      const double wkey = wave_max(key);
+      const bool tie = key == wkey;
+      const unsigned long long bal = __ballot(tie);
+      const int wcode = __popcll(bal) == 1
+                            ? __builtin_amdgcn_readlane(code, __ffsll(static_cast<long long>(bal)) - 1)
+                            : wave_min(tie ? code : 0x7fffffff);
+      LD* slot = cand + ((c & 1) * 4 + w) * kCand;
+      if (code == wcode) {
+        slot[0] = wkey;
+        slot[1] = int_in_double(wcode);
+#pragma unroll
+        for (int j = c; j < kNB; ++j) slot[2 + j] = P[j];
+      }
+      __syncthreads();
+      // the winner among the four waves' candidates: largest key, then the
+      // smallest code
+      const LD* set = cand + (c & 1) * 4 * kCand;
+      double bk = set[0];
+      int bc = int_of_double(set[1]), bw = 0;
+#pragma unroll
+      for (int v = 1; v < 4; ++v) {
+        const double kv = set[v * kCand];
+        const int cv = int_of_double(set[v * kCand + 1]);
+        if (kv > bk || (kv == bk && cv < bc)) {
+          bk = kv;
+          bc = cv;
+          bw = v;
+        }
+      }
+      const int pv = bc >> 8, qs = bc & 255;
+      if (t == 0) lds(W.piv)[k] = pv;
+      if (q == qs) {
+        pq = k;
+      } else if (pq == k) {
+        pq = pv;
+      }
+      const LD* pr = set + bw * kCand + 2;
+      const double akk = pr[c];
+      if (akk == 0.0) {
+        if (!info) info = k + 1;
+        if (t == 0) lds(W.zpm)[k0 / kNB] |= 1 << c;
+      } else if (pq > k) {
+        // below the pivot: multiplier, and the multiplier times the pivot
+        // row's later entries subtracted
+        const double l = P[c] / akk;
+        P[c] = l;
+#pragma unroll
+        for (int j = c + 1; j < kNB; ++j)
+          if (j < nb) P[j] = P[j] - l * pr[j];
+      }
+    }
+  }
+  if (q < n) {
+#pragma unroll
+    for (int c = 0; c < kNB; ++c)
+      if (c < nb) M[(k0 + c) * ld + q] = P[c];
+  }
+  if (q < ld) lds(W.pos)[q] = pq;
+  if (pq >= 0) lds(W.perm)[pq] = q;
+  if (t == 0) lds(W.ired)[15] = info;
+}
+
+__device__ __forceinline__ int lu_w(double* M, int n, int ld, const Wide& W) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int np = (n + kNB - 1) / kNB;
+  const int cnt2 = kNB * ld / 2;
+  auto* pos = lds(W.pos);
+  auto* perm = lds(W.perm);
+  auto* zpm = lds(W.zpm);
+  auto* ired = lds(W.ired);
+  if (t < ld) {
+    pos[t] = t < n ? t : -1;
+    perm[t] = t;
+  }
+  if (t < 32) zpm[t] = 0;
+  if (t == 0) ired[15] = 0;
+  double A0[kCW], A1[kCW], A2[kCW], A3[kCW];
+  load_cols(A0, A1, A2, A3, M, n, ld, 0, min(kNB, n));
+  dv2 R[kPre];
+  int g = 0;   // finished blocks applied so far: block g is in buffer g & 1
+  __syncthreads();
+  for (int p = 0; p < np; ++p) {
+    const int k0 = p * kNB, nb = min(kNB, n - k0);
+    int ps[kRS];
+#pragma unroll
+    for (int s = 0; s < kRS; ++s) {
+      const int q = lane + 64 * s;
+      ps[s] = q < ld ? pos[q] : -1;
+    }
+    // the panel's columns were loaded during the previous factorisation:
+    // wait for them here, once, not inside the block loop where the next
+    // block's loads are in flight
+    each_slot(A0, A1, A2, A3, [&](double (&row)[kCW], const int s) {
+#pragma unroll
+      for (int cc = 0; cc < kCW; ++cc) asm volatile("" : "+v"(row[cc]));
+    });
+    if (p == 1) {
+      // the first finished block, not loaded ahead
+      block_load(M, cnt2, R);
+      block_store_t(W.panel, ld, cnt2, R);
+      __syncthreads();
+    }
+    for (int b = 0; b < p; ++b) {
+      const int kb = b * kNB;
+      // the next block: (p, b + 1), or the first one of panel p + 1
+      const bool more = b + 1 < p || p + 1 < np;
+      if (more) block_load(M + (b + 1 < p ? kb + kNB : 0) * ld, cnt2, R);
+      const int zm = __builtin_amdgcn_readfirstlane(zpm[b]);
+      apply_block(A0, A1, A2, A3, ps, (g & 1) ? W.U12 : W.panel, kb, zm, W);
+      if (more) block_store_t((g & 1) ? W.panel : W.U12, ld, cnt2, R);
+      __syncthreads();
+      ++g;
+    }
+    // the panel to wave 0, as rows of kNB, through the buffer the last block used
+    double* H = (g & 1) ? W.panel : W.U12;
+    auto* HL = lds(H);
+    each_slot(A0, A1, A2, A3, [&](double (&row)[kCW], const int s) {
+      const int q = lane + 64 * s;
+#pragma unroll
+      for (int cc = 0; cc < kCW; ++cc)
+        if (q < n) HL[q * kNB + kCW * w + cc] = row[cc];
+    });
+    __syncthreads();
+    if (p + 1 < np) load_cols(A0, A1, A2, A3, M, n, ld, k0 + kNB, min(kNB, n - k0 - kNB));
+    factor_panel(M, H, n, ld, k0, nb, W);
+    __syncthreads();
+  }
+  return ired[15];
+}
+
+// x = M^-1 b with the factors of lu_w. b (LDS) is overwritten: the
+// substitutions run in place in physical row order; x (LDS, distinct from b)
+// receives the solution. Forward substitution in blocks of kSB columns (each
+// element receives its terms in ascending column order), then backward in
+// blocks from the bottom. Wave 0 solves the block's triangle, the solved
+// value of each step broadcast by readlane (the backward steps multiply by
+// the diagonal's reciprocal); every thread then updates its physical row,
+// whose kSB loads were issued before the triangle.
 constexpr int kSB = 32;
 
-__device__ void solve_w(const double* M, int n, int ld, const Wide& W, const double* b, double* x) {
+__device__ __forceinline__ void solve_w(const double* Mg, int n, int ld, const Wide& W, double* bg, double* xg) {
+  const auto* M = glb(Mg);
+  auto* b = lds(bg);
+  auto* x = lds(xg);
+  auto* xb = lds(W.panel);                // the block's solved values
+  const auto* perm = lds(W.perm);
   const int t = threadIdx.x;
-  if (t < n) x[t] = b[W.perm[t]];
-  __syncthreads();
+  const int pt = t < n ? lds(W.pos)[t] : -1;   // logical position of physical row t
   for (int k0 = 0; k0 < n; k0 += kSB) {
     const int nb = min(kSB, n - k0);
+    const bool below = pt >= k0 + nb;
+    double lv[kSB];
+#pragma unroll
+    for (int q = 0; q < kSB; ++q) lv[q] = (below && q < nb) ? M[(k0 + q) * ld + t] : 0.0;
     if (t < 64) {
+      const int r = t < nb ? perm[k0 + t] : 0;
       double lc[kSB];
 #pragma unroll
-      for (int q = 0; q < kSB; ++q) lc[q] = (q + 1 < nb && t > q && t < nb) ? M[(k0 + q) * ld + k0 + t] : 0.0;
-      double xv = t < nb ? x[k0 + t] : 0.0;
+      for (int q = 0; q < kSB; ++q) lc[q] = (q + 1 < nb && t > q && t < nb) ? M[(k0 + q) * ld + r] : 0.0;
+      double xv = t < nb ? b[r] : 0.0;
 #pragma unroll
       for (int q = 0; q + 1 < kSB; ++q) {
         if (q + 1 < nb) {
-          const double z = __shfl(xv, q);
+          const double z = rl_d(xv, q);
           if (t > q && t < nb) xv = xv - lc[q] * z;
         }
       }
-      if (t < nb) x[k0 + t] = xv;
+      if (t < nb) {
+        b[r] = xv;
+        xb[t] = xv;
+      }
     }
     __syncthreads();
-    for (int r = k0 + nb + t; r < n; r += kT) {
-      double lv[kSB];
-#pragma unroll
-      for (int q = 0; q < kSB; ++q) lv[q] = q < nb ? M[(k0 + q) * ld + r] : 0.0;
-      double a = x[r];
+    if (below) {
+      double a = b[t];
 #pragma unroll
       for (int q = 0; q < kSB; ++q)
-        if (q < nb) a = a - lv[q] * x[k0 + q];
-      x[r] = a;
+        if (q < nb) a = a - lv[q] * xb[q];
+      b[t] = a;
     }
     __syncthreads();
   }
   for (int k0 = ((n - 1) / kSB) * kSB; k0 >= 0; k0 -= kSB) {
     const int nb = min(kSB, n - k0);
+    const bool above = pt >= 0 && pt < k0;
+    double uv[kSB];
+#pragma unroll
+    for (int q = 0; q < kSB; ++q) uv[q] = (above && q < nb) ? M[(k0 + q) * ld + t] : 0.0;
     if (t < 64) {
+      const int r = t < nb ? perm[k0 + t] : 0;
       double uc[kSB];
 #pragma unroll
-      for (int q = 0; q < kSB; ++q) uc[q] = (q < nb && t < q) ? M[(k0 + q) * ld + k0 + t] : 0.0;
-      const double dg = t < nb ? M[(k0 + t) * ld + k0 + t] : 1.0;
-      double xv = t < nb ? x[k0 + t] : 0.0;
+      for (int q = 0; q < kSB; ++q) uc[q] = (q < nb && t < q) ? M[(k0 + q) * ld + r] : 0.0;
+      // the diagonal's reciprocals, all lanes at once
+      const double rdg = 1.0 / (t < nb ? M[(k0 + t) * ld + r] : 1.0);
+      double xv = t < nb ? b[r] : 0.0;
 #pragma unroll
       for (int q = kSB - 1; q >= 0; --q) {
         if (q < nb) {
-          const double d = (t == q) ? xv / dg : 0.0;
-          const double z = __shfl(d, q);
+          const double z = rl_d(xv, q) * rl_d(rdg, q);
           if (t == q) {
             xv = z;
           } else if (t < q) {
@@ -484,21 +768,23 @@ __device__ void solve_w(const double* M, int n, int ld, const Wide& W, const dou
           }
         }
       }
-      if (t < nb) x[k0 + t] = xv;
+      if (t < nb) {
+        b[r] = xv;
+        xb[t] = xv;
+      }
     }
     __syncthreads();
-    for (int r = t; r < k0; r += kT) {
-      double uv[kSB];
-#pragma unroll
-      for (int q = 0; q < kSB; ++q) uv[q] = q < nb ? M[(k0 + q) * ld + r] : 0.0;
-      double a = x[r];
+    if (above) {
+      double a = b[t];
 #pragma unroll
       for (int q = 0; q < kSB; ++q)
-        if (q < nb) a = a - uv[q] * x[k0 + q];
-      x[r] = a;
+        if (q < nb) a = a - uv[q] * xb[q];
+      b[t] = a;
     }
     __syncthreads();
   }
+  if (t < n) x[t] = b[perm[t]];
+  __syncthreads();
 }
 
 // ---- the state without the bath gas ----------------------------------------------
@@ -531,7 +817,7 @@ __device__ void reduce_bath_w(double* J, int ns, int ld) {
 // GEN: honour the forward-difference Jacobian and the state without the bath
 // gas; without it both are compiled out.
 template <int SCHEME, bool GEN>
-__device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, double* J, double* M, int ld,
+__device__ __forceinline__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, double* J, double* M, int ld,
                             const OptsDev& o, double p, double dt, double& hio, int& nacc_o, int& nrej_o,
                             int& status_o) {
   using TB = Tab<SCHEME>;
@@ -686,7 +972,7 @@ __device__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, 
 }
 
 template <int SCHEME, bool GEN>
-__device__ void run_cell_w(const IntegrateArgs& a, const MechLds& L, const Wide& W, double* J, double* M,
+__device__ __forceinline__ void run_cell_w(const IntegrateArgs& a, const MechLds& L, const Wide& W, double* J, double* M,
                            long long cell) {
   const int ns = a.m.ns, n = ns + 1, w2 = ns + 2;
   const int t = threadIdx.x;
@@ -804,7 +1090,7 @@ __global__ void __launch_bounds__(256) k_lu_wide(LuArgs a) {
     const int info = lu_w(M, n, ld, W);
     for (long long e = t; e < nn; e += kT) {
       const int i = static_cast<int>(e / n), j = static_cast<int>(e - static_cast<long long>(i) * n);
-      a.A[m * nn + e] = M[j * ld + i];
+      a.A[m * nn + e] = M[j * ld + W.perm[i]];
     }
     if (t < n) a.piv[m * n + t] = W.piv[t];
     if (t == 0) a.info[m] = info;

@@ -1,17 +1,18 @@
 """Bounds of the large-mechanism LU's index arithmetic, checked on the CPU.
 
-`tests/wide_lu_bounds.c` replays the workgroup kernel's blocked LU and
-triangular solves (their loops, bounds and guards, thread by thread) with
-every LDS and HBM buffer allocated on its own at exactly the kernel's size,
-built with AddressSanitizer. It is run for every state size of the workgroup
-kernel (65..256), so every tail panel width appears, including 1 (n = 1 mod
-12) and a full last panel (n = 0 mod 12). Two layouts are covered: the
-shipped one (12-column panels, U block in LDS) and a 16-column panel whose
-trailing update reads the U block from the matrix in HBM. The matrices
-include pivots taken from the last row at every step and a singular last
-column. The replica's factors and pivots must equal the oracle's in every
-bit, which shows that it follows the kernel's arithmetic; its solutions must
-match the oracle's to rounding.
+`tests/wide_lu_bounds.c` replays the workgroup kernel's left-looking blocked
+LU and its triangular solves (their loops, bounds and guards, thread by
+thread, with the waves' register arrays as arrays per thread) with every LDS
+and HBM buffer allocated on its own at exactly the kernel's size, built with
+AddressSanitizer. It is run for every state size of the workgroup kernel
+(65..256), so every tail panel width appears, including 1 (n = 1 mod 12) and
+a full last panel (n = 0 mod 12), and every count of row slots per lane (2, 3
+and 4). The matrices include pivots taken from the last row at every step, a
+singular last column and a zero pivot in the middle, whose multipliers must
+not reach later columns. Uninitialised buffers and the padding rows hold
+NaN, so any use of them shows in the factors. The replica's factors and
+pivots must equal the oracle's in every bit, which shows that it follows the
+kernel's arithmetic; its solutions must match the oracle's to rounding.
 """
 import os
 import shutil
@@ -56,36 +57,36 @@ def _read(path):
     return out
 
 
-# the shipped layout at every size of the workgroup kernel; the other layouts
-# and matrix patterns on a window of sizes that holds every tail width twice
-CASES = [(12, 0, 0, 65, 256)] + [
-    (panel, u_hbm, pattern, 140, 140 + 2 * panel - 1)
-    for panel, u_hbm in [(12, 0), (16, 1), (16, 0), (12, 1)] for pattern in (0, 1, 3)
-    if (panel, u_hbm, pattern) != (12, 0, 0)] + [(16, 1, 0, 224, 256), (12, 0, 1, 225, 256)]
+# every size of the workgroup kernel on random matrices; the other patterns on
+# windows of sizes that hold every tail width, and the largest sizes
+CASES = [(0, 65, 256)] + [(pattern, 140, 163) for pattern in (1, 2, 3, 4)] + [(1, 233, 256), (4, 233, 256)]
 
 
-@pytest.mark.parametrize("panel,u_hbm,pattern,n_lo,n_hi", CASES)
-def test_wide_lu_in_bounds(exe, panel, u_hbm, pattern, n_lo, n_hi):
+@pytest.mark.parametrize("pattern,n_lo,n_hi", CASES)
+def test_wide_lu_in_bounds(exe, pattern, n_lo, n_hi):
     path, d = exe
-    out = os.path.join(d, "r_%d_%d_%d_%d.bin" % (panel, u_hbm, pattern, n_lo))
+    out = os.path.join(d, "r_%d_%d.bin" % (pattern, n_lo))
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:exitcode=23")
-    r = subprocess.run([path, out, str(panel), str(u_hbm), str(n_lo), str(n_hi), str(pattern)], env=env,
-                       capture_output=True, text=True)
+    r = subprocess.run([path, out, str(n_lo), str(n_hi), str(pattern)], env=env, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     res = _read(out)
     assert [n for n, *_ in res] == list(range(n_lo, n_hi + 1))
     tails = set()
     for n, ld, info, A, F, piv, x in res:
-        tails.add((n - 1) % panel + 1)
+        tails.add((n - 1) % 12 + 1)
         LU, piv_o, info_o = O.lu(A)
         assert info == info_o, n
         assert np.array_equal(piv, piv_o), n
         assert np.array_equal(F, LU), n          # same operations in the same order
         if pattern == 1:
             assert (piv[:-1] == n - 1).all(), n
+        if pattern == 2:
+            assert (piv == np.arange(n)).all(), n
         if info == 0:
             xo = O.lu_solve(LU, piv_o, np.arange(n, dtype=float) + 1)
             assert np.max(np.abs(x - xo)) <= 1e-12 * np.max(np.abs(xo)), n
+        elif pattern == 3:
+            assert info == n, n
         else:
-            assert pattern == 3 and info == n
-    assert tails == set(range(1, panel + 1))   # every tail panel width, 1 and full included
+            assert pattern == 4 and info == n // 2 + 1, n
+    assert tails == set(range(1, 13))   # every tail panel width, 1 and full included

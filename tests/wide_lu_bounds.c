@@ -1,26 +1,33 @@
 /* Host replica of the index arithmetic of the workgroup kernel's blocked LU
- * and triangular solves (lu_w and solve_w of the large-mechanism integrator),
- * for bounds checking under AddressSanitizer. TEST INFRASTRUCTURE ONLY.
+ * and triangular solves (lu_w, factor_panel and solve_w of the
+ * large-mechanism integrator), for bounds checking under AddressSanitizer.
+ * TEST INFRASTRUCTURE ONLY.
  *
  * Every buffer the kernel touches is allocated on its own, at exactly the
- * size the kernel's layout gives it: in LDS the panel (nb_max ld doubles), the
- * U block (nb_max ld doubles, absent when the U block is read from HBM), piv,
- * perm and sig (ld ints each) and the reduction scratch (16 ints); in HBM the
- * matrix slot (n columns of ld doubles). An access outside any of them stops
- * the program with an ASan report.
+ * size the kernel's layout gives it: in LDS the two 12-column buffers
+ * (kNB ld doubles each, one block of multipliers as rows of 12, or the panel
+ * as rows of 12), the waves' U-block tables (4 x 36 doubles), piv, perm and
+ * pos (ld ints each), the reduction scratch (16 ints), the zero-pivot masks
+ * (32 ints) and the solve vectors (ld doubles each); in HBM the matrix slot (n
+ * columns of ld doubles). An access outside any of them stops the program
+ * with an ASan report.
  *
- * The 256 threads of the workgroup run one after the other inside each phase
- * between two barriers; wave 0's panel factorisation runs its 64 lanes in
- * lock step, with the butterfly reduction replaced by the value it computes
- * (largest |a|, NaN rule, ties to the lowest row). The loops, bounds and
- * guards follow the kernel's source line for line, so that the factors come
- * out equal to an unblocked LU in every bit (the test checks that too).
+ * The kernel's registers are arrays per thread. The 256 threads run one after
+ * the other inside each phase between two barriers; a wave's lanes run in
+ * lock step where they exchange values (DPP broadcasts read before any lane
+ * writes, reductions replaced by the value they compute: largest key, then
+ * the smallest (position, row) code among the lanes holding it). The
+ * loops, bounds and guards follow the kernel's source, so that the factors
+ * come out equal to an unblocked LU in every bit (the test checks that too).
  *
- * Usage: wide_lu_bounds <out.bin> <panel width> <u_in_hbm 0|1> <n_lo> <n_hi> <pattern>
+ * Usage: wide_lu_bounds <out.bin> <n_lo> <n_hi> <pattern>
  * pattern 0: random matrices; 1: every pivot is the last row; 2: no pivoting
- * (diagonally dominant); 3: column n-1 made zero (a singular last column).
- * For each n it writes n, ld, info, the input (row-major), the factors
- * (row-major), piv and the solution of A x = b for b_i = i + 1.
+ * (diagonally dominant); 3: column n-1 made zero (a singular last column);
+ * 4: column n/2 made zero (a zero pivot inside the matrix, whose multipliers
+ * must not be applied to later columns).
+ * For each n it writes n, ld, info, the input (row-major), the factors in
+ * logical row order (row-major), piv and the solution of A x = b for
+ * b_i = i + 1.
  */
 #include <math.h>
 #include <stdint.h>
@@ -28,158 +35,260 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { T = 256, SB = 32 };
-
-static int NB;          /* panel width of the variant */
-static int U_HBM;       /* U block read from the matrix (1) or from LDS (0) */
+enum { T = 256, NB = 12, RS = 4, CW = 3, PRE = 6, SB = 32 };
 
 typedef struct {
-  double *panel, *U12;
-  int *piv, *perm, *sig, *ired;
+  double *panel, *U12, *b, *x, *ub;
+  int *piv, *perm, *pos, *ired, *zpm;
 } lds_t;
+
+/* registers of the 256 threads */
+static double A[T][RS][CW];
+static double R[T][PRE][2];
+static int PS[T][RS];
 
 static int imin(int a, int b) { return a < b ? a : b; }
 
-static int lu_w(double* M, int n, int ld, lds_t* W) {
-  for (int t = 0; t < T; ++t)
-    if (t < ld) W->perm[t] = t;
-  int info = 0;
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    const int nb = imin(NB, n - k0);
-    for (int t = 0; t < T; ++t)
-      if (t < ld) {
-        const int in = t >= k0 && t < n;
-        for (int c = 0; c < nb; ++c) W->panel[c * ld + t] = in ? M[(k0 + c) * ld + t] : 0.0;
-        W->sig[t] = t;
-      }
-    /* wave 0: panel factorisation, lanes in lock step */
-    for (int c = 0; c < nb; ++c) {
-      const int k = k0 + c;
-      double* pc = W->panel + c * ld;
-      double key = -1.0;
-      int idx = 1 << 30;
-      for (int t = 0; t < 64; ++t)
-        for (int r = k + t; r < n; r += 64) {
-          const double av = fabs(pc[r]);
-          const double kv = (av != av) ? (r == k ? INFINITY : -1.0) : av;
-          if (kv > key || (kv == key && r < idx)) {
-            key = kv;
-            idx = r;
-          }
-        }
-      const int pv = idx;
-      W->piv[k] = pv;
-      {
-        const int tmp = W->perm[k];
-        W->perm[k] = W->perm[pv];
-        W->perm[pv] = tmp;
-        const int tms = W->sig[k];
-        W->sig[k] = W->sig[pv];
-        W->sig[pv] = tms;
-      }
-      if (pv != k)
-        for (int t = 0; t < 64; ++t)
-          if (t < nb) {
-            double* q = W->panel + t * ld;
-            const double tmp = q[k];
-            q[k] = q[pv];
-            q[pv] = tmp;
-          }
-      const double akk = pc[k];
-      if (akk == 0.0) {
-        if (!info) info = k + 1;
-        continue;
-      }
-      for (int t = 0; t < 64; ++t)
-        for (int r = k + 1 + t; r < n; r += 64) {
-          const double l = pc[r] / akk;
-          pc[r] = l;
-          for (int c2 = c + 1; c2 < nb; ++c2) {
-            double* q = W->panel + c2 * ld;
-            q[r] = q[r] - l * q[k];
-          }
-        }
+static void block_load(int t, const double* src, int cnt2) {
+  for (int i = 0; i < PRE; ++i) {
+    const int e = t + T * i;
+    R[t][i][0] = R[t][i][1] = 0.0;
+    if (e < cnt2) {
+      R[t][i][0] = src[2 * e];
+      R[t][i][1] = src[2 * e + 1];
     }
-    W->ired[15] = info;
-    info = W->ired[15];
-    for (int t = 0; t < T; ++t)
-      if (t < ld && t >= k0 && t < n)
-        for (int c = 0; c < nb; ++c) M[(k0 + c) * ld + t] = W->panel[c * ld + t];
-    /* interchanges on the other columns: sources of a column read before any
-     * destination of it is written */
-    for (int t = 0; t < T; ++t)
-      for (int j = t; j < n; j += T) {
-        if (j >= k0 && j < k0 + nb) continue;
-        double* col = M + j * ld;
-        double va[16], vb[16];
-        for (int c = 0; c < NB; ++c) {
-          const int ia = k0 + c, ib = c < nb ? W->piv[k0 + c] : ia;
-          va[c] = (c < nb && W->sig[ia] != ia) ? col[W->sig[ia]] : 0.0;
-          vb[c] = (c < nb && W->sig[ib] != ib) ? col[W->sig[ib]] : 0.0;
+  }
+}
+
+static void block_store_t(int t, double* dst, int ld, int cnt2) {
+  for (int i = 0; i < PRE; ++i) {
+    const int e = t + T * i;
+    if (e < cnt2) {
+      const int m = (2 * e) / ld, q = 2 * e - m * ld;
+      dst[q * NB + m] = R[t][i][0];
+      dst[(q + 1) * NB + m] = R[t][i][1];
+    }
+  }
+}
+
+static void load_cols(int t, const double* M, int n, int ld, int k0, int nb) {
+  const int lane = t & 63, w = t >> 6;
+  for (int s = 0; s < RS; ++s) {
+    const int q = lane + 64 * s;
+    for (int cc = 0; cc < CW; ++cc) {
+      const int c = CW * w + cc;
+      A[t][s][cc] = (q < n && c < nb) ? M[(k0 + c) * ld + q] : 0.0;
+    }
+  }
+}
+
+/* one finished block (multipliers as rows of 12 in Lt) applied to wave w's
+ * three panel columns */
+static void apply_block(int w, const double* Lt, int kb, int zm, lds_t* W) {
+  double* Tw = W->ub + 36 * w;
+  for (int lane = 0; lane < 64; ++lane) {
+    const int t = 64 * w + lane;
+    for (int s = 0; s < RS; ++s) {
+      const int m = PS[t][s] - kb;
+      if (m >= 0 && m < NB)
+        for (int cc = 0; cc < CW; ++cc) Tw[m * CW + cc] = A[t][s][cc];
+    }
+  }
+  /* triangle: lane 16 cc + m holds row m, column cc */
+  double x[64], lr[64][NB];
+  for (int lane = 0; lane < 64; ++lane) {
+    const int cc = lane >> 4, m = lane & 15;
+    const int act = cc < CW && m < NB;
+    x[lane] = act ? Tw[m * CW + cc] : 0.0;
+    const int q = act ? W->perm[kb + m] : 0;
+    for (int j = 0; j < NB; ++j) lr[lane][j] = Lt[q * NB + j];
+  }
+  for (int j = 0; j + 1 < NB; ++j) {
+    if ((zm >> j) & 1) continue;
+    double u[64];
+    for (int lane = 0; lane < 64; ++lane) u[lane] = x[(lane & ~15) + j];
+    for (int lane = 0; lane < 64; ++lane) {
+      const double y = x[lane] - lr[lane][j] * u[lane];
+      x[lane] = (lane & 15) > j ? y : x[lane];
+    }
+  }
+  for (int lane = 0; lane < 64; ++lane) {
+    const int cc = lane >> 4, m = lane & 15;
+    if (cc < CW && m < NB) Tw[m * CW + cc] = x[lane];
+  }
+  double U[NB][CW];
+  for (int j = 0; j < NB; ++j)
+    for (int c = 0; c < CW; ++c) U[j][c] = Tw[j * CW + c];
+  for (int lane = 0; lane < 64; ++lane) {
+    const int t = 64 * w + lane;
+    for (int s = 0; s < RS; ++s) {
+      const int q = lane + 64 * s;
+      const int rel = PS[t][s] - kb;
+      if (rel >= NB) {
+        double l[NB];
+        for (int j = 0; j < NB; ++j) l[j] = Lt[q * NB + j];
+        for (int j = 0; j < NB; ++j) {
+          if ((zm >> j) & 1) continue;
+          for (int c = 0; c < CW; ++c) A[t][s][c] = A[t][s][c] - l[j] * U[j][c];
         }
-        for (int c = 0; c < NB; ++c) {
-          const int ia = k0 + c, ib = c < nb ? W->piv[k0 + c] : ia;
-          if (c < nb && W->sig[ia] != ia) col[ia] = va[c];
-          if (c < nb && W->sig[ib] != ib) col[ib] = vb[c];
-        }
-      }
-    const int j0 = k0 + nb, m = n - j0;
-    if (m > 0) {
-      for (int t = 0; t < T; ++t)
-        for (int j = j0 + t; j < n; j += T) {
-          double* col = M + j * ld;
-          double x[16];
-          for (int q = 0; q < NB; ++q) x[q] = q < nb ? col[k0 + q] : 0.0;
-          for (int q = 1; q < NB; ++q)
-            for (int q2 = 0; q2 < q; ++q2)
-              if (q < nb) x[q] = x[q] - W->panel[q2 * ld + k0 + q] * x[q2];
-          for (int q = 0; q < NB; ++q)
-            if (q < nb) {
-              col[k0 + q] = x[q];
-              if (!U_HBM) W->U12[(j - j0) * NB + q] = x[q];
-            }
-        }
-      for (int t = 0; t < T; ++t) {
-        const int half = t >> 7, rl = t & 127;
-        for (int rb = rl; rb < m; rb += 128) {
-          const int r = j0 + rb;
-          double lr[16];
-          for (int q = 0; q < NB; ++q) lr[q] = q < nb ? W->panel[q * ld + r] : 0.0;
-          for (int jb = half; jb < m; jb += 16) {
-            double av[8];
-            for (int i = 0; i < 8; ++i) {
-              const int jj = jb + 2 * i;
-              av[i] = jj < m ? M[(j0 + jj) * ld + r] : 0.0;
-            }
-            for (int i = 0; i < 8; ++i) {
-              const int jj = jb + 2 * i;
-              if (jj < m) {
-                for (int q = 0; q < NB; ++q) {
-                  if (q >= nb) continue;
-                  const double u = U_HBM ? M[(j0 + jj) * ld + k0 + q] : W->U12[jj * NB + q];
-                  av[i] = av[i] - lr[q] * u;
-                }
-                M[(j0 + jj) * ld + r] = av[i];
-              }
-            }
-          }
-        }
+      } else if (rel >= 0) {
+        for (int c = 0; c < CW; ++c) A[t][s][c] = Tw[rel * CW + c];
       }
     }
   }
-  return info;
 }
 
-static void solve_w(const double* M, int n, int ld, const lds_t* W, const double* b, double* x) {
-  for (int t = 0; t < T; ++t)
-    if (t < n) x[t] = b[W->perm[t]];
+/* all four waves: thread t holds physical row t of the panel; the waves'
+ * candidates go through the U-block table area (2 x 4 x 14 doubles) */
+static void factor_panel(double* M, const double* H, int n, int ld, int k0, int nb, lds_t* W) {
+  static double P[T][NB];
+  int pq[T];
+  int info = W->ired[15];
+  double* cand = W->ub;
+  for (int t = 0; t < T; ++t) {
+    pq[t] = t < n ? W->pos[t] : -1;
+    for (int j = 0; j < NB; ++j) P[t][j] = t < n ? H[t * NB + j] : 0.0;
+  }
+  for (int c = 0; c < nb; ++c) {
+    const int k = k0 + c;
+    double key[T];
+    int code[T];
+    for (int t = 0; t < T; ++t) {
+      const double av = fabs(P[t][c]);
+      key[t] = pq[t] < k ? -1.0 : (av != av ? (pq[t] == k ? INFINITY : -1.0) : av);
+      code[t] = pq[t] * 256 + t;
+    }
+    for (int w = 0; w < 4; ++w) {
+      double wkey = key[64 * w];
+      for (int l = 1; l < 64; ++l)
+        if (key[64 * w + l] > wkey) wkey = key[64 * w + l];
+      int wcode = 0x7fffffff;
+      for (int l = 0; l < 64; ++l)
+        if (key[64 * w + l] == wkey && code[64 * w + l] < wcode) wcode = code[64 * w + l];
+      double* slot = cand + ((c & 1) * 4 + w) * (2 + NB);
+      for (int l = 0; l < 64; ++l) {
+        const int t = 64 * w + l;
+        if (code[t] == wcode) {
+          slot[0] = wkey;
+          slot[1] = (double)wcode;   /* the kernel keeps the int's bits; the value is what matters here */
+          for (int j = c; j < NB; ++j) slot[2 + j] = P[t][j];
+        }
+      }
+    }
+    const double* set = cand + (c & 1) * 4 * (2 + NB);
+    double bk = set[0];
+    int bc = (int)set[1], bw = 0;
+    for (int v = 1; v < 4; ++v) {
+      const double kv = set[v * (2 + NB)];
+      const int cv = (int)set[v * (2 + NB) + 1];
+      if (kv > bk || (kv == bk && cv < bc)) {
+        bk = kv;
+        bc = cv;
+        bw = v;
+      }
+    }
+    const int pv = bc >> 8, qs = bc & 255;
+    W->piv[k] = pv;
+    for (int t = 0; t < T; ++t) {
+      if (t == qs) pq[t] = k;
+      else if (pq[t] == k) pq[t] = pv;
+    }
+    const double* pr = set + bw * (2 + NB) + 2;
+    const double akk = pr[c];
+    if (akk == 0.0) {
+      if (!info) info = k + 1;
+      W->zpm[k0 / NB] |= 1 << c;
+    } else {
+      for (int t = 0; t < T; ++t)
+        if (pq[t] > k) {
+          const double l = P[t][c] / akk;
+          P[t][c] = l;
+          for (int j = c + 1; j < NB; ++j)
+            if (j < nb) P[t][j] = P[t][j] - l * pr[j];
+        }
+    }
+  }
+  for (int t = 0; t < T; ++t) {
+    if (t < n)
+      for (int c = 0; c < NB; ++c)
+        if (c < nb) M[(k0 + c) * ld + t] = P[t][c];
+    if (t < ld) W->pos[t] = pq[t];
+    if (pq[t] >= 0) W->perm[pq[t]] = t;
+  }
+  W->ired[15] = info;
+}
+
+static int lu_w(double* M, int n, int ld, lds_t* W) {
+  const int np = (n + NB - 1) / NB;
+  const int cnt2 = NB * ld / 2;
+  for (int t = 0; t < T; ++t) {
+    if (t < ld) {
+      W->pos[t] = t < n ? t : -1;
+      W->perm[t] = t;
+    }
+    if (t < 32) W->zpm[t] = 0;
+    if (t == 0) W->ired[15] = 0;
+    load_cols(t, M, n, ld, 0, imin(NB, n));
+  }
+  int g = 0;
+  for (int p = 0; p < np; ++p) {
+    const int k0 = p * NB, nb = imin(NB, n - k0);
+    for (int t = 0; t < T; ++t)
+      for (int s = 0; s < RS; ++s) {
+        const int q = (t & 63) + 64 * s;
+        PS[t][s] = q < ld ? W->pos[q] : -1;
+      }
+    if (p == 1) {
+      for (int t = 0; t < T; ++t) block_load(t, M, cnt2);
+      for (int t = 0; t < T; ++t) block_store_t(t, W->panel, ld, cnt2);
+    }
+    for (int b = 0; b < p; ++b) {
+      const int kb = b * NB;
+      const double* Lt = (g & 1) ? W->U12 : W->panel;
+      const int more = b + 1 < p || p + 1 < np;
+      if (more)
+        for (int t = 0; t < T; ++t) block_load(t, M + (b + 1 < p ? kb + NB : 0) * ld, cnt2);
+      const int zm = W->zpm[b];
+      for (int w = 0; w < 4; ++w) apply_block(w, Lt, kb, zm, W);
+      if (more)
+        for (int t = 0; t < T; ++t) block_store_t(t, (g & 1) ? W->panel : W->U12, ld, cnt2);
+      ++g;
+    }
+    double* H = (g & 1) ? W->panel : W->U12;
+    for (int t = 0; t < T; ++t) {
+      const int lane = t & 63, w = t >> 6;
+      for (int s = 0; s < RS; ++s) {
+        const int q = lane + 64 * s;
+        for (int cc = 0; cc < CW; ++cc)
+          if (q < n) H[q * NB + CW * w + cc] = A[t][s][cc];
+      }
+    }
+    if (p + 1 < np)
+      for (int t = 0; t < T; ++t) load_cols(t, M, n, ld, k0 + NB, imin(NB, n - k0 - NB));
+    factor_panel(M, H, n, ld, k0, nb, W);
+  }
+  return W->ired[15];
+}
+
+static void solve_w(const double* M, int n, int ld, lds_t* W) {
+  double* b = W->b;
+  double* x = W->x;
+  double* xb = W->panel;
+  int pt[T];
+  for (int t = 0; t < T; ++t) pt[t] = t < n ? W->pos[t] : -1;
   for (int k0 = 0; k0 < n; k0 += SB) {
     const int nb = imin(SB, n - k0);
-    /* wave 0: lower triangle of the block, lanes in lock step */
+    static double lv[T][SB];
+    for (int t = 0; t < T; ++t) {
+      const int below = pt[t] >= k0 + nb;
+      for (int q = 0; q < SB; ++q) lv[t][q] = (below && q < nb) ? M[(k0 + q) * ld + t] : 0.0;
+    }
     double lc[64][SB], xv[64];
+    int r[64];
     for (int t = 0; t < 64; ++t) {
-      for (int q = 0; q < SB; ++q) lc[t][q] = (q + 1 < nb && t > q && t < nb) ? M[(k0 + q) * ld + k0 + t] : 0.0;
-      xv[t] = t < nb ? x[k0 + t] : 0.0;
+      r[t] = t < nb ? W->perm[k0 + t] : 0;
+      for (int q = 0; q < SB; ++q) lc[t][q] = (q + 1 < nb && t > q && t < nb) ? M[(k0 + q) * ld + r[t]] : 0.0;
+      xv[t] = t < nb ? b[r[t]] : 0.0;
     }
     for (int q = 0; q + 1 < SB; ++q)
       if (q + 1 < nb) {
@@ -188,45 +297,56 @@ static void solve_w(const double* M, int n, int ld, const lds_t* W, const double
           if (t > q && t < nb) xv[t] = xv[t] - lc[t][q] * z;
       }
     for (int t = 0; t < 64; ++t)
-      if (t < nb) x[k0 + t] = xv[t];
+      if (t < nb) {
+        b[r[t]] = xv[t];
+        xb[t] = xv[t];
+      }
     for (int t = 0; t < T; ++t)
-      for (int r = k0 + nb + t; r < n; r += T) {
-        double lv[SB];
-        for (int q = 0; q < SB; ++q) lv[q] = q < nb ? M[(k0 + q) * ld + r] : 0.0;
-        double a = x[r];
+      if (pt[t] >= k0 + nb) {
+        double a = b[t];
         for (int q = 0; q < SB; ++q)
-          if (q < nb) a = a - lv[q] * x[k0 + q];
-        x[r] = a;
+          if (q < nb) a = a - lv[t][q] * xb[q];
+        b[t] = a;
       }
   }
   for (int k0 = ((n - 1) / SB) * SB; k0 >= 0; k0 -= SB) {
     const int nb = imin(SB, n - k0);
-    double uc[64][SB], dg[64], xv[64];
+    static double uv[T][SB];
+    for (int t = 0; t < T; ++t) {
+      const int above = pt[t] >= 0 && pt[t] < k0;
+      for (int q = 0; q < SB; ++q) uv[t][q] = (above && q < nb) ? M[(k0 + q) * ld + t] : 0.0;
+    }
+    double uc[64][SB], rdg[64], xv[64];
+    int r[64];
     for (int t = 0; t < 64; ++t) {
-      for (int q = 0; q < SB; ++q) uc[t][q] = (q < nb && t < q) ? M[(k0 + q) * ld + k0 + t] : 0.0;
-      dg[t] = t < nb ? M[(k0 + t) * ld + k0 + t] : 1.0;
-      xv[t] = t < nb ? x[k0 + t] : 0.0;
+      r[t] = t < nb ? W->perm[k0 + t] : 0;
+      for (int q = 0; q < SB; ++q) uc[t][q] = (q < nb && t < q) ? M[(k0 + q) * ld + r[t]] : 0.0;
+      rdg[t] = 1.0 / (t < nb ? M[(k0 + t) * ld + r[t]] : 1.0);
+      xv[t] = t < nb ? b[r[t]] : 0.0;
     }
     for (int q = SB - 1; q >= 0; --q)
       if (q < nb) {
-        const double z = xv[q] / dg[q];
+        const double z = xv[q] * rdg[q];
         for (int t = 0; t < 64; ++t) {
           if (t == q) xv[t] = z;
           else if (t < q) xv[t] = xv[t] - uc[t][q] * z;
         }
       }
     for (int t = 0; t < 64; ++t)
-      if (t < nb) x[k0 + t] = xv[t];
+      if (t < nb) {
+        b[r[t]] = xv[t];
+        xb[t] = xv[t];
+      }
     for (int t = 0; t < T; ++t)
-      for (int r = t; r < k0; r += T) {
-        double uv[SB];
-        for (int q = 0; q < SB; ++q) uv[q] = q < nb ? M[(k0 + q) * ld + r] : 0.0;
-        double a = x[r];
+      if (pt[t] >= 0 && pt[t] < k0) {
+        double a = b[t];
         for (int q = 0; q < SB; ++q)
-          if (q < nb) a = a - uv[q] * x[k0 + q];
-        x[r] = a;
+          if (q < nb) a = a - uv[t][q] * xb[q];
+        b[t] = a;
       }
   }
+  for (int t = 0; t < T; ++t)
+    if (t < n) x[t] = b[W->perm[t]];
 }
 
 static uint64_t rng = 0x9e3779b97f4a7c15ull;
@@ -238,29 +358,33 @@ static double urand(void) {
 }
 
 int main(int argc, char** argv) {
-  if (argc != 7) {
-    fprintf(stderr, "usage: %s out.bin panel u_in_hbm n_lo n_hi pattern\n", argv[0]);
+  if (argc != 5) {
+    fprintf(stderr, "usage: %s out.bin n_lo n_hi pattern\n", argv[0]);
     return 2;
   }
-  NB = atoi(argv[2]);
-  U_HBM = atoi(argv[3]);
-  const int n_lo = atoi(argv[4]), n_hi = atoi(argv[5]), pattern = atoi(argv[6]);
-  if (NB < 1 || NB > 16 || n_lo < 1 || n_hi > 256 || n_lo > n_hi) return 2;
+  const int n_lo = atoi(argv[2]), n_hi = atoi(argv[3]), pattern = atoi(argv[4]);
+  if (n_lo < 13 || n_hi > 256 || n_lo > n_hi || pattern < 0 || pattern > 4) return 2;
   FILE* f = fopen(argv[1], "wb");
   if (!f) return 2;
   for (int n = n_lo; n <= n_hi; ++n) {
     const int ld = (n + 15) & ~15;
     double* M = (double*)malloc(sizeof(double) * (size_t)n * ld);
-    double* A = (double*)malloc(sizeof(double) * (size_t)n * n);
+    double* Ain = (double*)malloc(sizeof(double) * (size_t)n * n);
     lds_t W;
     W.panel = (double*)malloc(sizeof(double) * (size_t)NB * ld);
-    W.U12 = U_HBM ? NULL : (double*)malloc(sizeof(double) * (size_t)NB * ld);
+    W.U12 = (double*)malloc(sizeof(double) * (size_t)NB * ld);
+    W.b = (double*)malloc(sizeof(double) * ld);
+    W.x = (double*)malloc(sizeof(double) * ld);
     W.piv = (int*)malloc(sizeof(int) * ld);
     W.perm = (int*)malloc(sizeof(int) * ld);
-    W.sig = (int*)malloc(sizeof(int) * ld);
+    W.pos = (int*)malloc(sizeof(int) * ld);
     W.ired = (int*)malloc(sizeof(int) * 16);
-    double* b = (double*)malloc(sizeof(double) * n);
-    double* x = (double*)malloc(sizeof(double) * n);
+    W.zpm = (int*)malloc(sizeof(int) * 32);
+    W.ub = (double*)malloc(sizeof(double) * 144);
+    /* uninitialised LDS and padding rows hold NaN: they must never be used */
+    for (int i = 0; i < NB * ld; ++i) W.panel[i] = W.U12[i] = NAN;
+    for (int i = 0; i < 144; ++i) W.ub[i] = NAN;
+    for (size_t i = 0; i < (size_t)n * ld; ++i) M[i] = NAN;
     if (pattern == 1) {
       /* A = P L U with |l| <= 1/2 below the unit diagonal: partial pivoting
        * picks the row holding L's row k, which P places at the current last
@@ -283,7 +407,7 @@ int main(int argc, char** argv) {
         for (int j = 0; j < n; ++j) {
           double v = 0.0;
           for (int q = 0; q < n; ++q) v += L[arr[p] * n + q] * U[q * n + j];
-          A[p * n + j] = v;
+          Ain[p * n + j] = v;
         }
       free(L); free(U); free(arr);
     } else {
@@ -292,24 +416,25 @@ int main(int argc, char** argv) {
           double v = urand();
           if (pattern == 2) v = (i == j) ? 4.0 * n : v;
           if (pattern == 3 && j == n - 1) v = 0.0;
-          A[i * n + j] = v;
+          if (pattern == 4 && j == n / 2) v = 0.0;
+          Ain[i * n + j] = v;
         }
     }
     for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) M[j * ld + i] = A[i * n + j];
+      for (int j = 0; j < n; ++j) M[j * ld + i] = Ain[i * n + j];
     const int info = lu_w(M, n, ld, &W);
-    for (int i = 0; i < n; ++i) b[i] = i + 1.0;
-    if (info == 0) solve_w(M, n, ld, &W, b, x);
-    else for (int i = 0; i < n; ++i) x[i] = 0.0;
+    for (int i = 0; i < ld; ++i) W.b[i] = i < n ? i + 1.0 : NAN;
+    if (info == 0) solve_w(M, n, ld, &W);
+    else for (int i = 0; i < n; ++i) W.x[i] = 0.0;
     int hdr[3] = {n, ld, info};
     fwrite(hdr, sizeof(int), 3, f);
-    fwrite(A, sizeof(double), (size_t)n * n, f);
+    fwrite(Ain, sizeof(double), (size_t)n * n, f);
     for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) fwrite(&M[j * ld + i], sizeof(double), 1, f);
+      for (int j = 0; j < n; ++j) fwrite(&M[j * ld + W.perm[i]], sizeof(double), 1, f);
     fwrite(W.piv, sizeof(int), n, f);
-    fwrite(x, sizeof(double), n, f);
-    free(M); free(A); free(W.panel); free(W.U12); free(W.piv); free(W.perm); free(W.sig); free(W.ired);
-    free(b); free(x);
+    fwrite(W.x, sizeof(double), n, f);
+    free(M); free(Ain); free(W.panel); free(W.U12); free(W.b); free(W.x);
+    free(W.piv); free(W.perm); free(W.pos); free(W.ired); free(W.zpm); free(W.ub);
   }
   fclose(f);
   return 0;
