@@ -522,12 +522,15 @@ __device__ __forceinline__ void apply_block(double (&A0)[kCW], double (&A1)[kCW]
 
 // All four waves: factor panel columns k0 .. k0 + nb - 1. The panel arrives in
 // LDS as rows of kNB doubles (H[q * kNB + c], physical row q); lane l of wave
-// w holds row q = 64 w + l in registers for the whole panel. At each column
-// every wave finds its best candidate (DPP reductions) and that row's lane
-// writes the candidate's key, code and remaining entries to the wave's LDS
-// slot (two sets, by column parity); after one barrier every lane picks the
-// same winner from the four slots, reads its row (a broadcast) and updates its
-// own row. Writes the panel to M and the positions to W.pos / W.perm.
+// w holds row q = 64 w + l in registers, rotated so that the current column
+// is always P[0] (the loop over columns then needs no run-time register
+// index). At each column every wave finds its best candidate (DPP
+// reductions) and that row's lane writes the candidate's key, code and row to
+// the wave's LDS slot (two sets, by column parity); after one barrier every
+// lane picks the same winner from the four slots, reads its row (a broadcast)
+// and updates its own row. The finished column goes to M; the row shifts by
+// one. Entries past the panel's last column are updated too but never stored.
+// Writes the positions to W.pos / W.perm.
 constexpr int kCand = 2 + kNB;   // per wave and parity: key, code, row entries
 
 __device__ __forceinline__ void factor_panel(double* Mg, const double* Hg, int n, int ld, int k0, int nb,
@@ -537,7 +540,7 @@ __device__ __forceinline__ void factor_panel(double* Mg, const double* Hg, int n
   const LD* H = lds(Hg);
   LD* cand = lds(W.ub);   // 2 x 4 x kCand doubles (the U-block tables are idle here)
   auto* M = glb(Mg);
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int t = threadIdx.x, w = t >> 6;
   const int q = t;        // this lane's physical row
   int pq = q < n ? lds(W.pos)[q] : -1;
   int info = lds(W.ired)[15];
@@ -551,72 +554,78 @@ __device__ __forceinline__ void factor_panel(double* Mg, const double* Hg, int n
       P[2 * j + 1] = q < n ? v.y : 0.0;
     }
   }
+  for (int c = 0; c < nb; ++c) {
+    const int k = k0 + c;
+    // first logical row of the largest |a| among rows k..n-1 (a NaN on the
+    // diagonal stays the pivot; elsewhere it never wins); code = logical
+    // position * 256 + physical row
+    const double av = fabs(P[0]);
+    const double key = pq < k ? -1.0 : (av != av ? (pq == k ? INFINITY : -1.0) : av);
+    const int code = pq * 256 + q;
+    const double wkey = wave_max(key);
+    const bool tie = key == wkey;
+    const unsigned long long bal = __ballot(tie);
+    const int wcode = __popcll(bal) == 1
+                          ? __builtin_amdgcn_readlane(code, __ffsll(static_cast<long long>(bal)) - 1)
+                          : wave_min(tie ? code : 0x7fffffff);
+    LD* slot = cand + ((c & 1) * 4 + w) * kCand;
+    if (code == wcode) {
+      slot[0] = wkey;
+      slot[1] = int_in_double(wcode);
+      LD2* r2 = reinterpret_cast<LD2*>(slot + 2);
 #pragma unroll
-  for (int c = 0; c < kNB; ++c) {
-    if (c < nb) {
-      const int k = k0 + c;
-      // first logical row of the largest |a| among rows k..n-1 (a NaN on the
-      // diagonal stays the pivot; elsewhere it never wins); code = logical
-      // position * 256 + physical row
-      const double av = fabs(P[c]);
-      const double key = pq < k ? -1.0 : (av != av ? (pq == k ? INFINITY : -1.0) : av);
-      const int code = pq * 256 + q;
-      const double wkey = wave_max(key);
-      const bool tie = key == wkey;
-      const unsigned long long bal = __ballot(tie);
-      const int wcode = __popcll(bal) == 1
-                            ? __builtin_amdgcn_readlane(code, __ffsll(static_cast<long long>(bal)) - 1)
-                            : wave_min(tie ? code : 0x7fffffff);
-      LD* slot = cand + ((c & 1) * 4 + w) * kCand;
-      if (code == wcode) {
-        slot[0] = wkey;
-        slot[1] = int_in_double(wcode);
+      for (int j = 0; j < kNB / 2; ++j) r2[j] = dv2{P[2 * j], P[2 * j + 1]};
+    }
+    __syncthreads();
+    // the winner among the four waves' candidates: largest key, then the
+    // smallest code
+    const LD* set = cand + (c & 1) * 4 * kCand;
+    double bk = set[0];
+    int bc = int_of_double(set[1]), bw = 0;
 #pragma unroll
-        for (int j = c; j < kNB; ++j) slot[2 + j] = P[j];
-      }
-      __syncthreads();
-      // the winner among the four waves' candidates: largest key, then the
-      // smallest code
-      const LD* set = cand + (c & 1) * 4 * kCand;
-      double bk = set[0];
-      int bc = int_of_double(set[1]), bw = 0;
-#pragma unroll
-      for (int v = 1; v < 4; ++v) {
-        const double kv = set[v * kCand];
-        const int cv = int_of_double(set[v * kCand + 1]);
-        if (kv > bk || (kv == bk && cv < bc)) {
-          bk = kv;
-          bc = cv;
-          bw = v;
-        }
-      }
-      const int pv = bc >> 8, qs = bc & 255;
-      if (t == 0) lds(W.piv)[k] = pv;
-      if (q == qs) {
-        pq = k;
-      } else if (pq == k) {
-        pq = pv;
-      }
-      const LD* pr = set + bw * kCand + 2;
-      const double akk = pr[c];
-      if (akk == 0.0) {
-        if (!info) info = k + 1;
-        if (t == 0) lds(W.zpm)[k0 / kNB] |= 1 << c;
-      } else if (pq > k) {
-        // below the pivot: multiplier, and the multiplier times the pivot
-        // row's later entries subtracted
-        const double l = P[c] / akk;
-        P[c] = l;
-#pragma unroll
-        for (int j = c + 1; j < kNB; ++j)
-          if (j < nb) P[j] = P[j] - l * pr[j];
+    for (int v = 1; v < 4; ++v) {
+      const double kv = set[v * kCand];
+      const int cv = int_of_double(set[v * kCand + 1]);
+      if (kv > bk || (kv == bk && cv < bc)) {
+        bk = kv;
+        bc = cv;
+        bw = v;
       }
     }
-  }
-  if (q < n) {
+    bw = __builtin_amdgcn_readfirstlane(bw);
+    const int pv = __builtin_amdgcn_readfirstlane(bc) >> 8, qs = __builtin_amdgcn_readfirstlane(bc) & 255;
+    if (t == 0) lds(W.piv)[k] = pv;
+    if (q == qs) {
+      pq = k;
+    } else if (pq == k) {
+      pq = pv;
+    }
+    double pr[kNB];
+    {
+      const LD2* r2 = reinterpret_cast<const LD2*>(set + bw * kCand + 2);
 #pragma unroll
-    for (int c = 0; c < kNB; ++c)
-      if (c < nb) M[(k0 + c) * ld + q] = P[c];
+      for (int j = 0; j < kNB / 2; ++j) {
+        const dv2 v = r2[j];
+        pr[2 * j] = v.x;
+        pr[2 * j + 1] = v.y;
+      }
+    }
+    const double akk = pr[0];
+    if (akk == 0.0) {
+      if (!info) info = k + 1;
+      if (t == 0) lds(W.zpm)[k0 / kNB] |= 1 << c;
+    } else if (pq > k) {
+      // below the pivot: multiplier, and the multiplier times the pivot
+      // row's later entries subtracted
+      const double l = P[0] / akk;
+      P[0] = l;
+#pragma unroll
+      for (int j = 1; j < kNB; ++j) P[j] = P[j] - l * pr[j];
+    }
+    if (q < n) M[k * ld + q] = P[0];
+#pragma unroll
+    for (int j = 0; j + 1 < kNB; ++j) P[j] = P[j + 1];
+    P[kNB - 1] = 0.0;
   }
   if (q < ld) lds(W.pos)[q] = pq;
   if (pq >= 0) lds(W.perm)[pq] = q;
