@@ -369,6 +369,7 @@ constexpr int kPre = 6;             // two-double loads per thread for one 12-co
 static_assert(kT == 256 && kNB == 12, "four waves of three panel columns each");
 
 __device__ __forceinline__ void block_load(const double* src, int cnt2, dv2 (&r)[kPre]) {
+  asm volatile("" : "+s"(src));   // addresses formed here, not hoisted and spilled
   const auto* s = glb(reinterpret_cast<const dv2*>(src));
 #pragma unroll
   for (int i = 0; i < kPre; ++i) {
@@ -407,6 +408,7 @@ __device__ __forceinline__ void each_slot(double (&r0)[C], double (&r1)[C], doub
 // beyond the panel as zero
 __device__ __forceinline__ void load_cols(double (&a0)[kCW], double (&a1)[kCW], double (&a2)[kCW],
                                           double (&a3)[kCW], const double* Mg, int n, int ld, int k0, int nb) {
+  asm volatile("" : "+s"(k0));    // addresses formed here, not hoisted and spilled
   const auto* M = glb(Mg);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   each_slot(a0, a1, a2, a3, [&](double (&row)[kCW], const int s) {
@@ -704,95 +706,125 @@ __device__ __forceinline__ int lu_w(double* M, int n, int ld, const Wide& W) {
 // substitutions run in place in physical row order; x (LDS, distinct from b)
 // receives the solution. Forward substitution in blocks of kSB columns (each
 // element receives its terms in ascending column order), then backward in
-// blocks from the bottom. Wave 0 solves the block's triangle, the solved
-// value of each step broadcast by readlane (the backward steps multiply by
-// the diagonal's reciprocal); every thread then updates its physical row,
-// whose kSB loads were issued before the triangle.
-constexpr int kSB = 32;
+// blocks from the bottom. Every thread loads its own physical row's entries
+// in the block's columns, two blocks ahead (three register sets, loads
+// issued unconditionally so that each wait is for one set only). The rows
+// inside the block hand theirs to wave 0 through LDS; wave 0 solves the
+// block's triangle, the solved value of each step broadcast by readlane (the
+// backward steps multiply by the diagonal's reciprocal); every thread then
+// updates its row.
+constexpr int kSB = 16;
 
-__device__ __forceinline__ void solve_w(const double* Mg, int n, int ld, const Wide& W, double* bg, double* xg) {
-  const auto* M = glb(Mg);
-  auto* b = lds(bg);
-  auto* x = lds(xg);
-  auto* xb = lds(W.panel);                // the block's solved values
-  const auto* perm = lds(W.perm);
+// row t's entries in columns k0 .. k0 + kSB - 1 (columns past n - 1 read
+// column n - 1; rows past ld - 1 read row 0: such values are never used)
+// (k0 passes through an empty asm so that the addresses are formed here, not
+// hoisted out of the loops and spilled)
+__device__ __forceinline__ void solve_load(const double* Mg, int n, int ld, int k0, double (&v)[kSB]) {
+  asm volatile("" : "+s"(k0));
+  const auto* M = glb(Mg) + (threadIdx.x < ld ? threadIdx.x : 0);
+#pragma unroll
+  for (int j = 0; j < kSB; ++j) v[j] = M[min(k0 + j, n - 1) * ld];
+}
+
+template <bool FWD>
+__device__ __forceinline__ void solve_block(int k0, int n, int pt, const double (&v)[kSB], const Wide& W,
+                                            __attribute__((address_space(3))) double* b) {
+  using LD = __attribute__((address_space(3))) double;
+  using LD2 = __attribute__((address_space(3))) dv2;
   const int t = threadIdx.x;
-  const int pt = t < n ? lds(W.pos)[t] : -1;   // logical position of physical row t
-  for (int k0 = 0; k0 < n; k0 += kSB) {
-    const int nb = min(kSB, n - k0);
-    const bool below = pt >= k0 + nb;
-    double lv[kSB];
+  const int nb = min(kSB, n - k0);
+  LD* T = lds(W.U12);                  // the block rows' entries, kSB x kSB
+  LD* xb = lds(W.ub);                  // the block's solved values
+  const int rel = pt - k0;
+  if (rel >= 0 && rel < nb) {
+    LD2* d = reinterpret_cast<LD2*>(T + rel * kSB);
 #pragma unroll
-    for (int q = 0; q < kSB; ++q) lv[q] = (below && q < nb) ? M[(k0 + q) * ld + t] : 0.0;
-    if (t < 64) {
-      const int r = t < nb ? perm[k0 + t] : 0;
-      double lc[kSB];
+    for (int j = 0; j < kSB / 2; ++j) d[j] = dv2{v[2 * j], v[2 * j + 1]};
+  }
+  __syncthreads();
+  if (t < 64) {
+    const int r = t < nb ? lds(W.perm)[k0 + t] : 0;
+    double lc[kSB];
+    {
+      const LD2* rr = reinterpret_cast<const LD2*>(T + (t < nb ? t : 0) * kSB);
 #pragma unroll
-      for (int q = 0; q < kSB; ++q) lc[q] = (q + 1 < nb && t > q && t < nb) ? M[(k0 + q) * ld + r] : 0.0;
-      double xv = t < nb ? b[r] : 0.0;
+      for (int j = 0; j < kSB / 2; ++j) {
+        const dv2 x = rr[j];
+        lc[2 * j] = x.x;
+        lc[2 * j + 1] = x.y;
+      }
+    }
+    double xv = t < nb ? b[r] : 0.0;
+    if (FWD) {
 #pragma unroll
-      for (int q = 0; q + 1 < kSB; ++q) {
-        if (q + 1 < nb) {
-          const double z = rl_d(xv, q);
-          if (t > q && t < nb) xv = xv - lc[q] * z;
+      for (int j = 0; j + 1 < kSB; ++j) {
+        if (j + 1 < nb) {
+          const double z = rl_d(xv, j);
+          if (t > j && t < nb) xv = xv - lc[j] * z;
         }
       }
-      if (t < nb) {
-        b[r] = xv;
-        xb[t] = xv;
-      }
-    }
-    __syncthreads();
-    if (below) {
-      double a = b[t];
-#pragma unroll
-      for (int q = 0; q < kSB; ++q)
-        if (q < nb) a = a - lv[q] * xb[q];
-      b[t] = a;
-    }
-    __syncthreads();
-  }
-  for (int k0 = ((n - 1) / kSB) * kSB; k0 >= 0; k0 -= kSB) {
-    const int nb = min(kSB, n - k0);
-    const bool above = pt >= 0 && pt < k0;
-    double uv[kSB];
-#pragma unroll
-    for (int q = 0; q < kSB; ++q) uv[q] = (above && q < nb) ? M[(k0 + q) * ld + t] : 0.0;
-    if (t < 64) {
-      const int r = t < nb ? perm[k0 + t] : 0;
-      double uc[kSB];
-#pragma unroll
-      for (int q = 0; q < kSB; ++q) uc[q] = (q < nb && t < q) ? M[(k0 + q) * ld + r] : 0.0;
+    } else {
       // the diagonal's reciprocals, all lanes at once
-      const double rdg = 1.0 / (t < nb ? M[(k0 + t) * ld + r] : 1.0);
-      double xv = t < nb ? b[r] : 0.0;
+      const double rdg = 1.0 / (t < nb ? T[t * kSB + t] : 1.0);
 #pragma unroll
-      for (int q = kSB - 1; q >= 0; --q) {
-        if (q < nb) {
-          const double z = rl_d(xv, q) * rl_d(rdg, q);
-          if (t == q) {
+      for (int j = kSB - 1; j >= 0; --j) {
+        if (j < nb) {
+          const double z = rl_d(xv, j) * rl_d(rdg, j);
+          if (t == j) {
             xv = z;
-          } else if (t < q) {
-            xv = xv - uc[q] * z;
+          } else if (t < j) {
+            xv = xv - lc[j] * z;
           }
         }
       }
-      if (t < nb) {
-        b[r] = xv;
-        xb[t] = xv;
-      }
     }
-    __syncthreads();
-    if (above) {
-      double a = b[t];
-#pragma unroll
-      for (int q = 0; q < kSB; ++q)
-        if (q < nb) a = a - uv[q] * xb[q];
-      b[t] = a;
+    if (t < nb) {
+      b[r] = xv;
+      xb[t] = xv;
     }
-    __syncthreads();
   }
-  if (t < n) x[t] = b[perm[t]];
+  __syncthreads();
+  if (FWD ? pt >= k0 + nb : (pt >= 0 && pt < k0)) {
+    double a = b[t];
+#pragma unroll
+    for (int j = 0; j < kSB; ++j)
+      if (j < nb) a = a - v[j] * xb[j];
+    b[t] = a;
+  }
+}
+
+__device__ __forceinline__ void solve_w(const double* M, int n, int ld, const Wide& W, double* bg, double* xg) {
+  auto* b = lds(bg);
+  auto* x = lds(xg);
+  const int t = threadIdx.x;
+  const int pt = t < n ? lds(W.pos)[t] : -1;   // logical position of physical row t
+  const int nblk = (n + kSB - 1) / kSB;
+  const int last = (nblk - 1) * kSB;
+  double v0[kSB], v1[kSB], v2[kSB];
+  // forward: blocks 0, 1, 2, ...; loads past the last block repeat it
+  solve_load(M, n, ld, 0, v0);
+  solve_load(M, n, ld, min(kSB, last), v1);
+  for (int i = 0; i < nblk; i += 3) {
+    solve_load(M, n, ld, min((i + 2) * kSB, last), v2);
+    solve_block<true>(i * kSB, n, pt, v0, W, b);
+    solve_load(M, n, ld, min((i + 3) * kSB, last), v0);
+    if (i + 1 < nblk) solve_block<true>((i + 1) * kSB, n, pt, v1, W, b);
+    solve_load(M, n, ld, min((i + 4) * kSB, last), v1);
+    if (i + 2 < nblk) solve_block<true>((i + 2) * kSB, n, pt, v2, W, b);
+  }
+  // backward: blocks nblk - 1, nblk - 2, ...; loads past the first repeat it
+  solve_load(M, n, ld, last, v0);
+  solve_load(M, n, ld, max(last - kSB, 0), v1);
+  for (int i = nblk - 1; i >= 0; i -= 3) {
+    solve_load(M, n, ld, max((i - 2) * kSB, 0), v2);
+    solve_block<false>(i * kSB, n, pt, v0, W, b);
+    solve_load(M, n, ld, max((i - 3) * kSB, 0), v0);
+    if (i - 1 >= 0) solve_block<false>((i - 1) * kSB, n, pt, v1, W, b);
+    solve_load(M, n, ld, max((i - 4) * kSB, 0), v1);
+    if (i - 2 >= 0) solve_block<false>((i - 2) * kSB, n, pt, v2, W, b);
+  }
+  __syncthreads();
+  if (t < n) x[t] = b[lds(W.perm)[t]];
   __syncthreads();
 }
 

@@ -35,7 +35,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { T = 256, NB = 12, RS = 4, CW = 3, PRE = 6, SB = 32 };
+enum { T = 256, NB = 12, RS = 4, CW = 3, PRE = 6, SB = 16 };
 
 typedef struct {
   double *panel, *U12, *b, *x, *ub;
@@ -270,83 +270,72 @@ static int lu_w(double* M, int n, int ld, lds_t* W) {
   return W->ired[15];
 }
 
-static void solve_w(const double* M, int n, int ld, lds_t* W) {
+/* one block of the substitution: every row's entries in the block's columns
+ * (loaded ahead; columns past n - 1 read column n - 1, rows past ld - 1 row
+ * 0), the block rows' entries through LDS (the second 12-column buffer) to
+ * wave 0, the triangle, then every row */
+static void solve_block(int fwd, int k0, int n, int ld, const double* M, lds_t* W, const int* pt) {
   double* b = W->b;
-  double* x = W->x;
-  double* xb = W->panel;
-  int pt[T];
-  for (int t = 0; t < T; ++t) pt[t] = t < n ? W->pos[t] : -1;
-  for (int k0 = 0; k0 < n; k0 += SB) {
-    const int nb = imin(SB, n - k0);
-    static double lv[T][SB];
-    for (int t = 0; t < T; ++t) {
-      const int below = pt[t] >= k0 + nb;
-      for (int q = 0; q < SB; ++q) lv[t][q] = (below && q < nb) ? M[(k0 + q) * ld + t] : 0.0;
-    }
-    double lc[64][SB], xv[64];
-    int r[64];
-    for (int t = 0; t < 64; ++t) {
-      r[t] = t < nb ? W->perm[k0 + t] : 0;
-      for (int q = 0; q < SB; ++q) lc[t][q] = (q + 1 < nb && t > q && t < nb) ? M[(k0 + q) * ld + r[t]] : 0.0;
-      xv[t] = t < nb ? b[r[t]] : 0.0;
-    }
-    for (int q = 0; q + 1 < SB; ++q)
-      if (q + 1 < nb) {
-        const double z = xv[q];
-        for (int t = 0; t < 64; ++t)
-          if (t > q && t < nb) xv[t] = xv[t] - lc[t][q] * z;
-      }
-    for (int t = 0; t < 64; ++t)
-      if (t < nb) {
-        b[r[t]] = xv[t];
-        xb[t] = xv[t];
-      }
-    for (int t = 0; t < T; ++t)
-      if (pt[t] >= k0 + nb) {
-        double a = b[t];
-        for (int q = 0; q < SB; ++q)
-          if (q < nb) a = a - lv[t][q] * xb[q];
-        b[t] = a;
-      }
+  double* xb = W->ub;
+  double* Tb = W->U12;
+  const int nb = imin(SB, n - k0);
+  static double v[T][SB];
+  for (int t = 0; t < T; ++t) {
+    const int r = t < ld ? t : 0;
+    for (int j = 0; j < SB; ++j) v[t][j] = M[imin(k0 + j, n - 1) * ld + r];
   }
-  for (int k0 = ((n - 1) / SB) * SB; k0 >= 0; k0 -= SB) {
-    const int nb = imin(SB, n - k0);
-    static double uv[T][SB];
-    for (int t = 0; t < T; ++t) {
-      const int above = pt[t] >= 0 && pt[t] < k0;
-      for (int q = 0; q < SB; ++q) uv[t][q] = (above && q < nb) ? M[(k0 + q) * ld + t] : 0.0;
-    }
-    double uc[64][SB], rdg[64], xv[64];
-    int r[64];
-    for (int t = 0; t < 64; ++t) {
-      r[t] = t < nb ? W->perm[k0 + t] : 0;
-      for (int q = 0; q < SB; ++q) uc[t][q] = (q < nb && t < q) ? M[(k0 + q) * ld + r[t]] : 0.0;
-      rdg[t] = 1.0 / (t < nb ? M[(k0 + t) * ld + r[t]] : 1.0);
-      xv[t] = t < nb ? b[r[t]] : 0.0;
-    }
-    for (int q = SB - 1; q >= 0; --q)
-      if (q < nb) {
-        const double z = xv[q] * rdg[q];
+  for (int t = 0; t < T; ++t) {
+    const int rel = pt[t] - k0;
+    if (rel >= 0 && rel < nb)
+      for (int j = 0; j < SB; ++j) Tb[rel * SB + j] = v[t][j];
+  }
+  double lc[64][SB], xv[64], rdg[64];
+  int r[64];
+  for (int t = 0; t < 64; ++t) {
+    r[t] = t < nb ? W->perm[k0 + t] : 0;
+    for (int j = 0; j < SB; ++j) lc[t][j] = Tb[(t < nb ? t : 0) * SB + j];
+    xv[t] = t < nb ? b[r[t]] : 0.0;
+    rdg[t] = fwd ? 0.0 : 1.0 / (t < nb ? Tb[t * SB + t] : 1.0);
+  }
+  if (fwd) {
+    for (int j = 0; j + 1 < SB; ++j)
+      if (j + 1 < nb) {
+        const double z = xv[j];
+        for (int t = 0; t < 64; ++t)
+          if (t > j && t < nb) xv[t] = xv[t] - lc[t][j] * z;
+      }
+  } else {
+    for (int j = SB - 1; j >= 0; --j)
+      if (j < nb) {
+        const double z = xv[j] * rdg[j];
         for (int t = 0; t < 64; ++t) {
-          if (t == q) xv[t] = z;
-          else if (t < q) xv[t] = xv[t] - uc[t][q] * z;
+          if (t == j) xv[t] = z;
+          else if (t < j) xv[t] = xv[t] - lc[t][j] * z;
         }
       }
-    for (int t = 0; t < 64; ++t)
-      if (t < nb) {
-        b[r[t]] = xv[t];
-        xb[t] = xv[t];
-      }
-    for (int t = 0; t < T; ++t)
-      if (pt[t] >= 0 && pt[t] < k0) {
-        double a = b[t];
-        for (int q = 0; q < SB; ++q)
-          if (q < nb) a = a - uv[t][q] * xb[q];
-        b[t] = a;
-      }
   }
+  for (int t = 0; t < 64; ++t)
+    if (t < nb) {
+      b[r[t]] = xv[t];
+      xb[t] = xv[t];
+    }
   for (int t = 0; t < T; ++t)
-    if (t < n) x[t] = b[W->perm[t]];
+    if (fwd ? pt[t] >= k0 + nb : (pt[t] >= 0 && pt[t] < k0)) {
+      double a = b[t];
+      for (int j = 0; j < SB; ++j)
+        if (j < nb) a = a - v[t][j] * xb[j];
+      b[t] = a;
+    }
+}
+
+static void solve_w(const double* M, int n, int ld, lds_t* W) {
+  int pt[T];
+  for (int t = 0; t < T; ++t) pt[t] = t < n ? W->pos[t] : -1;
+  const int nblk = (n + SB - 1) / SB;
+  for (int i = 0; i < nblk; ++i) solve_block(1, SB * i, n, ld, M, W, pt);
+  for (int i = nblk - 1; i >= 0; --i) solve_block(0, SB * i, n, ld, M, W, pt);
+  for (int t = 0; t < T; ++t)
+    if (t < n) W->x[t] = W->b[W->perm[t]];
 }
 
 static uint64_t rng = 0x9e3779b97f4a7c15ull;
