@@ -103,6 +103,23 @@ __device__ __forceinline__ double bsum(double v, double* red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Loads of J for the chain rule, in batches of kJB: species rows of column t
+// (row t of the species block) or of row t (column t); indices past the last
+// species read the last one (such values are never used), so that every
+// load is issued and each wait covers one batch. The start passes through an
+// empty asm so that the addresses are formed here.
+constexpr int kJB = 16;
+__device__ __forceinline__ void jrow_load(const double* J, int ns, int ld, int t, int k0, double (&v)[kJB]) {
+  asm volatile("" : "+s"(k0));
+#pragma unroll
+  for (int q = 0; q < kJB; ++q) v[q] = J[(1 + min(k0 + q, ns - 1)) * ld + t];
+}
+__device__ __forceinline__ void jcol_load(const double* J, int ns, int ld, int t, int q0, double (&v)[kJB]) {
+  asm volatile("" : "+s"(q0));
+#pragma unroll
+  for (int q = 0; q < kJB; ++q) v[q] = J[t * ld + 1 + min(q0 + q, ns - 1)];
+}
+
 // ---- right-hand side and analytical Jacobian ----------------------------------
 // f = dy/dt at y (LDS vector); with JAC also J = df/dy, column-major in HBM:
 // element (i, j) at J[j * ld + i]. Thread t owns state component t (0 = T,
@@ -206,15 +223,20 @@ __device__ __forceinline__ void rhs_w(const MechArgs& A, const MechLds& L, const
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   double sv = 0.0;
   if (sp) {
-    // four accumulators (k mod 4), eight loads in flight
+    // four accumulators (k mod 4); batches of kJB loads, the next batch in
+    // flight while one is used
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < ns; k0 += 8) {
-      double v[8];
+    double v0[kJB], v1[kJB];
+    jrow_load(J, ns, ld, t, 0, v0);
+    for (int k0 = 0; k0 < ns; k0 += 2 * kJB) {
+      jrow_load(J, ns, ld, t, k0 + kJB, v1);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = k0 + q < ns ? J[(1 + k0 + q) * ld + t] : 0.0;
+      for (int q = 0; q < kJB; ++q)
+        if (k0 + q < ns) a[q & 3] = fma(v0[q], W.C[k0 + q], a[q & 3]);
+      jrow_load(J, ns, ld, t, k0 + 2 * kJB, v0);
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (k0 + q < ns) a[q & 3] = fma(v[q], W.C[k0 + q], a[q & 3]);
+      for (int q = 0; q < kJB; ++q)
+        if (k0 + kJB + q < ns) a[q & 3] = fma(v1[q], W.C[k0 + kJB + q], a[q & 3]);
     }
     sv = ((a[0] + a[1]) + (a[2] + a[3])) + td * Ctot;
   }
@@ -223,15 +245,19 @@ __device__ __forceinline__ void rhs_w(const MechArgs& A, const MechLds& L, const
   const double dQdT = bsum(sp ? cpR * kR * om + hRT * kR * T * (wT - sv / T) : 0.0, W.red);
   double JT = 0.0;
   if (sp) {
-    const double* col = J + t * ld + 1;    // column t, rows 1..ns
+    // column t, rows 1..ns
     double c[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int q0 = 0; q0 < ns; q0 += 8) {
-      double v[8];
+    double v0[kJB], v1[kJB];
+    jcol_load(J, ns, ld, t, 0, v0);
+    for (int q0 = 0; q0 < ns; q0 += 2 * kJB) {
+      jcol_load(J, ns, ld, t, q0 + kJB, v1);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = q0 + q < ns ? col[q0 + q] : 0.0;
+      for (int q = 0; q < kJB; ++q)
+        if (q0 + q < ns) c[q & 3] = fma(W.hRT[q0 + q], v0[q], c[q & 3]);
+      jcol_load(J, ns, ld, t, q0 + 2 * kJB, v0);
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q0 + q < ns) c[q & 3] = fma(W.hRT[q0 + q], v[q], c[q & 3]);
+      for (int q = 0; q < kJB; ++q)
+        if (q0 + kJB + q < ns) c[q & 3] = fma(W.hRT[q0 + kJB + q], v1[q], c[q & 3]);
     }
     const double cs = (c[0] + c[1]) + (c[2] + c[3]);
     const double dQdY = kR * T * ((rho * rWs) * (cs + HT) - (Wbar * rWs) * HS);
@@ -241,12 +267,11 @@ __device__ __forceinline__ void rhs_w(const MechArgs& A, const MechLds& L, const
   __syncthreads();
   if (sp) {
     const double Wi_rho = A.W[s] / rho;
-    for (int k0 = 0; k0 < ns; k0 += 8) {
-      double v[8];
+    // the next batch is loaded before this one is written back; the two
+    // never overlap (a clamped load past the last species is not used)
+    auto upd = [&](const double (&v)[kJB], int k0) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = k0 + q < ns ? J[(1 + k0 + q) * ld + t] : 0.0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < kJB; ++q) {
         const int k = k0 + q;
         if (k < ns) {
           const double rWk = L.rW[k];
@@ -255,6 +280,14 @@ __device__ __forceinline__ void rhs_w(const MechArgs& A, const MechLds& L, const
           J[(1 + k) * ld + t] = Wi_rho * dw + fY * Wbar * rWk;
         }
       }
+    };
+    double v0[kJB], v1[kJB];
+    jrow_load(J, ns, ld, t, 0, v0);
+    for (int k0 = 0; k0 < ns; k0 += 2 * kJB) {
+      jrow_load(J, ns, ld, t, k0 + kJB, v1);
+      upd(v0, k0);
+      jrow_load(J, ns, ld, t, k0 + 2 * kJB, v0);
+      upd(v1, k0 + kJB);
     }
     J[t] = Wi_rho * (wT - sv / T) + fY / T;   // (t, 0)
     J[t * ld] = JT;                           // (0, t)
@@ -404,19 +437,24 @@ __device__ __forceinline__ void each_slot(double (&r0)[C], double (&r1)[C], doub
   f(r3, 3);
 }
 
-// this wave's panel columns (k0 + 3w + cc) from M, rows beyond n and columns
-// beyond the panel as zero
+// this wave's panel columns (k0 + 3w + cc) of the matrix, rows beyond n and
+// columns beyond the panel as zero. With FORM the source is J and the
+// matrix is g I - J, formed here: each column of M is read in its original
+// form only once, by this load.
+template <bool FORM>
 __device__ __forceinline__ void load_cols(double (&a0)[kCW], double (&a1)[kCW], double (&a2)[kCW],
-                                          double (&a3)[kCW], const double* Mg, int n, int ld, int k0, int nb) {
+                                          double (&a3)[kCW], const double* Sg, double g, int n, int ld, int k0,
+                                          int nb) {
   asm volatile("" : "+s"(k0));    // addresses formed here, not hoisted and spilled
-  const auto* M = glb(Mg);
+  const auto* S = glb(Sg);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   each_slot(a0, a1, a2, a3, [&](double (&row)[kCW], const int s) {
     const int q = lane + 64 * s;
 #pragma unroll
     for (int cc = 0; cc < kCW; ++cc) {
       const int c = kCW * w + cc;
-      row[cc] = (q < n && c < nb) ? M[(k0 + c) * ld + q] : 0.0;
+      const double v = (q < n && c < nb) ? S[(k0 + c) * ld + q] : 0.0;
+      row[cc] = FORM ? ((q == k0 + c ? g : 0.0) - v) : v;
     }
   });
 }
@@ -634,7 +672,10 @@ __device__ __forceinline__ void factor_panel(double* Mg, const double* Hg, int n
   if (t == 0) lds(W.ired)[15] = info;
 }
 
-__device__ __forceinline__ int lu_w(double* M, int n, int ld, const Wide& W) {
+// With FORM, the matrix is gm I - J (J: n x n, the same layout) and is formed
+// from J as its columns are first read; M then receives only the factors.
+template <bool FORM>
+__device__ __forceinline__ int lu_w(double* M, const double* J, double gm, int n, int ld, const Wide& W) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int np = (n + kNB - 1) / kNB;
   const int cnt2 = kNB * ld / 2;
@@ -649,7 +690,7 @@ __device__ __forceinline__ int lu_w(double* M, int n, int ld, const Wide& W) {
   if (t < 32) zpm[t] = 0;
   if (t == 0) ired[15] = 0;
   double A0[kCW], A1[kCW], A2[kCW], A3[kCW];
-  load_cols(A0, A1, A2, A3, M, n, ld, 0, min(kNB, n));
+  load_cols<FORM>(A0, A1, A2, A3, FORM ? J : M, gm, n, ld, 0, min(kNB, n));
   dv2 R[kPre];
   int g = 0;   // finished blocks applied so far: block g is in buffer g & 1
   __syncthreads();
@@ -695,7 +736,7 @@ __device__ __forceinline__ int lu_w(double* M, int n, int ld, const Wide& W) {
         if (q < n) HL[q * kNB + kCW * w + cc] = row[cc];
     });
     __syncthreads();
-    if (p + 1 < np) load_cols(A0, A1, A2, A3, M, n, ld, k0 + kNB, min(kNB, n - k0 - kNB));
+    if (p + 1 < np) load_cols<FORM>(A0, A1, A2, A3, FORM ? J : M, gm, n, ld, k0 + kNB, min(kNB, n - k0 - kNB));
     factor_panel(M, H, n, ld, k0, nb, W);
     __syncthreads();
   }
@@ -916,20 +957,10 @@ __device__ __forceinline__ void integrate_w(const MechArgs& A, const MechLds& L,
       status = 2;
       break;
     }
+    // M = g I - J, formed by the LU as it first reads each column
     const double g = 1.0 / (TB::gamma * hc);
-    if (t < ld) {
-      // eight independent loads in flight per thread
-      for (int c0 = 0; c0 < n; c0 += 8) {
-        double v[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = c0 + q < n ? J[(c0 + q) * ld + t] : 0.0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (c0 + q < n) M[(c0 + q) * ld + t] = (t == c0 + q ? g : 0.0) - v[q];
-      }
-    }
     __syncthreads();
-    const int info = lu_w(M, n, ld, W);
+    const int info = lu_w<true>(M, J, g, n, ld, W);
     ++att;
     if (info) {
       status = 4;
@@ -1128,7 +1159,7 @@ __global__ void __launch_bounds__(256) k_lu_wide(LuArgs a) {
       M[j * ld + i] = a.A[m * nn + e];
     }
     __syncthreads();
-    const int info = lu_w(M, n, ld, W);
+    const int info = lu_w<false>(M, nullptr, 0.0, n, ld, W);
     for (long long e = t; e < nn; e += kT) {
       const int i = static_cast<int>(e / n), j = static_cast<int>(e - static_cast<long long>(i) * n);
       a.A[m * nn + e] = M[j * ld + W.perm[i]];

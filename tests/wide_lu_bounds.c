@@ -20,7 +20,10 @@
  * loops, bounds and guards follow the kernel's source, so that the factors
  * come out equal to an unblocked LU in every bit (the test checks that too).
  *
- * Usage: wide_lu_bounds <out.bin> <n_lo> <n_hi> <pattern>
+ * Usage: wide_lu_bounds <out.bin> <n_lo> <n_hi> <pattern> [form]
+ * form 1: the LU receives J (the generated matrix) in its own slot and forms
+ * g I - J (g = 2.5) as it reads the columns, as the integrator does; the
+ * written input is then g I - J, formed with the same expression.
  * pattern 0: random matrices; 1: every pivot is the last row; 2: no pivoting
  * (diagonally dominant); 3: column n-1 made zero (a singular last column);
  * 4: column n/2 made zero (a zero pivot inside the matrix, whose multipliers
@@ -71,13 +74,15 @@ static void block_store_t(int t, double* dst, int ld, int cnt2) {
   }
 }
 
-static void load_cols(int t, const double* M, int n, int ld, int k0, int nb) {
+/* form: the source is J and the matrix g I - J is formed as it is read */
+static void load_cols(int t, const double* S, int form, double g, int n, int ld, int k0, int nb) {
   const int lane = t & 63, w = t >> 6;
   for (int s = 0; s < RS; ++s) {
     const int q = lane + 64 * s;
     for (int cc = 0; cc < CW; ++cc) {
       const int c = CW * w + cc;
-      A[t][s][cc] = (q < n && c < nb) ? M[(k0 + c) * ld + q] : 0.0;
+      const double v = (q < n && c < nb) ? S[(k0 + c) * ld + q] : 0.0;
+      A[t][s][cc] = form ? ((q == k0 + c ? g : 0.0) - v) : v;
     }
   }
 }
@@ -218,7 +223,7 @@ static void factor_panel(double* M, const double* H, int n, int ld, int k0, int 
   W->ired[15] = info;
 }
 
-static int lu_w(double* M, int n, int ld, lds_t* W) {
+static int lu_w(double* M, const double* J, double gm, int form, int n, int ld, lds_t* W) {
   const int np = (n + NB - 1) / NB;
   const int cnt2 = NB * ld / 2;
   for (int t = 0; t < T; ++t) {
@@ -228,7 +233,7 @@ static int lu_w(double* M, int n, int ld, lds_t* W) {
     }
     if (t < 32) W->zpm[t] = 0;
     if (t == 0) W->ired[15] = 0;
-    load_cols(t, M, n, ld, 0, imin(NB, n));
+    load_cols(t, form ? J : M, form, gm, n, ld, 0, imin(NB, n));
   }
   int g = 0;
   for (int p = 0; p < np; ++p) {
@@ -264,7 +269,7 @@ static int lu_w(double* M, int n, int ld, lds_t* W) {
       }
     }
     if (p + 1 < np)
-      for (int t = 0; t < T; ++t) load_cols(t, M, n, ld, k0 + NB, imin(NB, n - k0 - NB));
+      for (int t = 0; t < T; ++t) load_cols(t, form ? J : M, form, gm, n, ld, k0 + NB, imin(NB, n - k0 - NB));
     factor_panel(M, H, n, ld, k0, nb, W);
   }
   return W->ired[15];
@@ -347,11 +352,13 @@ static double urand(void) {
 }
 
 int main(int argc, char** argv) {
-  if (argc != 5) {
-    fprintf(stderr, "usage: %s out.bin n_lo n_hi pattern\n", argv[0]);
+  if (argc != 5 && argc != 6) {
+    fprintf(stderr, "usage: %s out.bin n_lo n_hi pattern [form]\n", argv[0]);
     return 2;
   }
   const int n_lo = atoi(argv[2]), n_hi = atoi(argv[3]), pattern = atoi(argv[4]);
+  const int form = argc == 6 ? atoi(argv[5]) : 0;
+  const double g = 2.5;
   if (n_lo < 13 || n_hi > 256 || n_lo > n_hi || pattern < 0 || pattern > 4) return 2;
   FILE* f = fopen(argv[1], "wb");
   if (!f) return 2;
@@ -409,9 +416,19 @@ int main(int argc, char** argv) {
           Ain[i * n + j] = v;
         }
     }
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) M[j * ld + i] = Ain[i * n + j];
-    const int info = lu_w(M, n, ld, &W);
+    double* J = (double*)malloc(sizeof(double) * (size_t)n * ld);
+    for (size_t i = 0; i < (size_t)n * ld; ++i) J[i] = NAN;
+    if (form) {
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          J[j * ld + i] = Ain[i * n + j];
+          Ain[i * n + j] = (i == j ? g : 0.0) - J[j * ld + i];
+        }
+    } else {
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) M[j * ld + i] = Ain[i * n + j];
+    }
+    const int info = lu_w(M, J, g, form, n, ld, &W);
     for (int i = 0; i < ld; ++i) W.b[i] = i < n ? i + 1.0 : NAN;
     if (info == 0) solve_w(M, n, ld, &W);
     else for (int i = 0; i < n; ++i) W.x[i] = 0.0;
@@ -422,7 +439,7 @@ int main(int argc, char** argv) {
       for (int j = 0; j < n; ++j) fwrite(&M[j * ld + W.perm[i]], sizeof(double), 1, f);
     fwrite(W.piv, sizeof(int), n, f);
     fwrite(W.x, sizeof(double), n, f);
-    free(M); free(Ain); free(W.panel); free(W.U12); free(W.b); free(W.x);
+    free(M); free(J); free(Ain); free(W.panel); free(W.U12); free(W.b); free(W.x);
     free(W.piv); free(W.perm); free(W.pos); free(W.ired); free(W.zpm); free(W.ub);
   }
   fclose(f);
