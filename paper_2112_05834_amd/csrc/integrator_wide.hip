@@ -401,14 +401,20 @@ constexpr int kCW = kNB / 4;        // panel columns per wave in the update
 constexpr int kPre = 6;             // two-double loads per thread for one 12-column block (ld <= 256)
 static_assert(kT == 256 && kNB == 12, "four waves of three panel columns each");
 
-__device__ __forceinline__ void block_load(const double* src, int cnt2, dv2 (&r)[kPre]) {
+// A finished block for the LU's update (kNB columns of ld from src): pairs of
+// rows that lie above the block (logical position < kb, or padding) are not
+// used, and read the block's first pair instead, so that every load is
+// issued while they cost no memory traffic of their own. mx[i] is the larger
+// logical position of this thread's i-th pair of rows (the same rows in every
+// block: pair i is element threadIdx.x + kT i of the column-major block).
+__device__ __forceinline__ void lu_block_load(const double* src, int cnt2, int kb, const int (&mx)[kPre],
+                                              dv2 (&r)[kPre]) {
   asm volatile("" : "+s"(src));   // addresses formed here, not hoisted and spilled
   const auto* s = glb(reinterpret_cast<const dv2*>(src));
 #pragma unroll
   for (int i = 0; i < kPre; ++i) {
-    const int e = static_cast<int>(threadIdx.x) + kT * i;
-    r[i] = dv2{0.0, 0.0};
-    if (e < cnt2) r[i] = s[e];
+    const int e = min(static_cast<int>(threadIdx.x) + kT * i, cnt2 - 1);
+    r[i] = s[mx[i] >= kb ? e : 0];
   }
 }
 // the block (column-major, kNB columns of ld) into LDS as rows of kNB:
@@ -487,14 +493,16 @@ __device__ __forceinline__ double row_share(double v, int src) {
 // panel columns. zm: the block's zero-pivot columns (skipped).
 __device__ __forceinline__ void apply_block(double (&A0)[kCW], double (&A1)[kCW], double (&A2)[kCW],
                                             double (&A3)[kCW], const int (&ps)[kRS], const double* Ltg, int kb,
-                                            int zm, const Wide& W) {
+                                            int zm, int n, const Wide& W) {
   using LD = __attribute__((address_space(3))) double;
   using LD2 = __attribute__((address_space(3))) dv2;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const LD* Lt = lds(Ltg);
   LD* T = lds(W.ub) + 36 * w;   // this wave's 12 x 3 table
   // the block's own rows (logical kb .. kb + 11) into the table
+  // (a slot with no row below n on any lane is skipped: its test is uniform)
   each_slot(A0, A1, A2, A3, [&](double (&row)[kCW], const int s) {
+    if (64 * s >= n) return;
     const int m = ps[s] - kb;
     if (m >= 0 && m < kNB) {
 #pragma unroll
@@ -535,6 +543,7 @@ __device__ __forceinline__ void apply_block(double (&A0)[kCW], double (&A1)[kCW]
 #pragma unroll
     for (int c = 0; c < kCW; ++c) U[j][c] = T[j * kCW + c];
   each_slot(A0, A1, A2, A3, [&](double (&row)[kCW], const int s) {
+    if (64 * s >= n) return;
     const int q = lane + 64 * s;
     const int rel = ps[s] - kb;
     if (rel >= kNB) {
@@ -702,6 +711,12 @@ __device__ __forceinline__ int lu_w(double* M, const double* J, double gm, int n
       const int q = lane + 64 * s;
       ps[s] = q < ld ? pos[q] : -1;
     }
+    int mx[kPre];   // positions of this thread's pairs of rows in the block loads
+#pragma unroll
+    for (int i = 0; i < kPre; ++i) {
+      const int q = (2 * min(t + kT * i, cnt2 - 1)) % ld;
+      mx[i] = max(pos[q], pos[q + 1]);
+    }
     // the panel's columns were loaded during the previous factorisation:
     // wait for them here, once, not inside the block loop where the next
     // block's loads are in flight
@@ -711,7 +726,7 @@ __device__ __forceinline__ int lu_w(double* M, const double* J, double gm, int n
     });
     if (p == 1) {
       // the first finished block, not loaded ahead
-      block_load(M, cnt2, R);
+      lu_block_load(M, cnt2, 0, mx, R);
       block_store_t(W.panel, ld, cnt2, R);
       __syncthreads();
     }
@@ -719,9 +734,9 @@ __device__ __forceinline__ int lu_w(double* M, const double* J, double gm, int n
       const int kb = b * kNB;
       // the next block: (p, b + 1), or the first one of panel p + 1
       const bool more = b + 1 < p || p + 1 < np;
-      if (more) block_load(M + (b + 1 < p ? kb + kNB : 0) * ld, cnt2, R);
+      if (more) lu_block_load(M + (b + 1 < p ? kb + kNB : 0) * ld, cnt2, b + 1 < p ? kb + kNB : 0, mx, R);
       const int zm = __builtin_amdgcn_readfirstlane(zpm[b]);
-      apply_block(A0, A1, A2, A3, ps, (g & 1) ? W.U12 : W.panel, kb, zm, W);
+      apply_block(A0, A1, A2, A3, ps, (g & 1) ? W.U12 : W.panel, kb, zm, n, W);
       if (more) block_store_t((g & 1) ? W.panel : W.U12, ld, cnt2, R);
       __syncthreads();
       ++g;
@@ -756,13 +771,15 @@ __device__ __forceinline__ int lu_w(double* M, const double* J, double gm, int n
 // updates its row.
 constexpr int kSB = 16;
 
-// row t's entries in columns k0 .. k0 + kSB - 1 (columns past n - 1 read
-// column n - 1; rows past ld - 1 read row 0: such values are never used)
-// (k0 passes through an empty asm so that the addresses are formed here, not
-// hoisted out of the loops and spilled)
-__device__ __forceinline__ void solve_load(const double* Mg, int n, int ld, int k0, double (&v)[kSB]) {
+// row t's entries in columns k0 .. k0 + kSB - 1 when the row takes part in
+// the block (need); columns past n - 1 read column n - 1, and rows that do not
+// take part read row 0, so that every load is issued (each wait then covers
+// one register set) while the rows left out cost no memory traffic of their
+// own; such values are never used. k0 passes through an empty asm so that
+// the addresses are formed here, not hoisted out of the loops and spilled.
+__device__ __forceinline__ void solve_load(const double* Mg, int n, int ld, int k0, bool need, double (&v)[kSB]) {
   asm volatile("" : "+s"(k0));
-  const auto* M = glb(Mg) + (threadIdx.x < ld ? threadIdx.x : 0);
+  const auto* M = glb(Mg) + (need ? threadIdx.x : 0);
 #pragma unroll
   for (int j = 0; j < kSB; ++j) v[j] = M[min(k0 + j, n - 1) * ld];
 }
@@ -843,25 +860,25 @@ __device__ __forceinline__ void solve_w(const double* M, int n, int ld, const Wi
   const int last = (nblk - 1) * kSB;
   double v0[kSB], v1[kSB], v2[kSB];
   // forward: blocks 0, 1, 2, ...; loads past the last block repeat it
-  solve_load(M, n, ld, 0, v0);
-  solve_load(M, n, ld, min(kSB, last), v1);
+  solve_load(M, n, ld, 0, pt >= 0, v0);
+  solve_load(M, n, ld, min(kSB, last), pt >= min(kSB, last), v1);
   for (int i = 0; i < nblk; i += 3) {
-    solve_load(M, n, ld, min((i + 2) * kSB, last), v2);
+    solve_load(M, n, ld, min((i + 2) * kSB, last), pt >= min((i + 2) * kSB, last), v2);
     solve_block<true>(i * kSB, n, pt, v0, W, b);
-    solve_load(M, n, ld, min((i + 3) * kSB, last), v0);
+    solve_load(M, n, ld, min((i + 3) * kSB, last), pt >= min((i + 3) * kSB, last), v0);
     if (i + 1 < nblk) solve_block<true>((i + 1) * kSB, n, pt, v1, W, b);
-    solve_load(M, n, ld, min((i + 4) * kSB, last), v1);
+    solve_load(M, n, ld, min((i + 4) * kSB, last), pt >= min((i + 4) * kSB, last), v1);
     if (i + 2 < nblk) solve_block<true>((i + 2) * kSB, n, pt, v2, W, b);
   }
   // backward: blocks nblk - 1, nblk - 2, ...; loads past the first repeat it
-  solve_load(M, n, ld, last, v0);
-  solve_load(M, n, ld, max(last - kSB, 0), v1);
+  solve_load(M, n, ld, last, pt >= 0 && pt < last + kSB, v0);
+  solve_load(M, n, ld, max(last - kSB, 0), pt >= 0 && pt < max(last - kSB, 0) + kSB, v1);
   for (int i = nblk - 1; i >= 0; i -= 3) {
-    solve_load(M, n, ld, max((i - 2) * kSB, 0), v2);
+    solve_load(M, n, ld, max((i - 2) * kSB, 0), pt >= 0 && pt < max((i - 2) * kSB, 0) + kSB, v2);
     solve_block<false>(i * kSB, n, pt, v0, W, b);
-    solve_load(M, n, ld, max((i - 3) * kSB, 0), v0);
+    solve_load(M, n, ld, max((i - 3) * kSB, 0), pt >= 0 && pt < max((i - 3) * kSB, 0) + kSB, v0);
     if (i - 1 >= 0) solve_block<false>((i - 1) * kSB, n, pt, v1, W, b);
-    solve_load(M, n, ld, max((i - 4) * kSB, 0), v1);
+    solve_load(M, n, ld, max((i - 4) * kSB, 0), pt >= 0 && pt < max((i - 4) * kSB, 0) + kSB, v1);
     if (i - 2 >= 0) solve_block<false>((i - 2) * kSB, n, pt, v2, W, b);
   }
   __syncthreads();

@@ -52,14 +52,15 @@ static int PS[T][RS];
 
 static int imin(int a, int b) { return a < b ? a : b; }
 
-static void block_load(int t, const double* src, int cnt2) {
+/* pairs of rows above the block (position < kb, or padding) read the first pair */
+static void block_load(int t, const double* src, int cnt2, int ld, int kb, const int* pos) {
   for (int i = 0; i < PRE; ++i) {
-    const int e = t + T * i;
-    R[t][i][0] = R[t][i][1] = 0.0;
-    if (e < cnt2) {
-      R[t][i][0] = src[2 * e];
-      R[t][i][1] = src[2 * e + 1];
-    }
+    int e = t + T * i;
+    if (e > cnt2 - 1) e = cnt2 - 1;
+    const int q = (2 * e) % ld;
+    const int need = pos[q] >= kb || pos[q + 1] >= kb;
+    R[t][i][0] = src[2 * (need ? e : 0)];
+    R[t][i][1] = src[2 * (need ? e : 0) + 1];
   }
 }
 
@@ -244,7 +245,7 @@ static int lu_w(double* M, const double* J, double gm, int form, int n, int ld, 
         PS[t][s] = q < ld ? W->pos[q] : -1;
       }
     if (p == 1) {
-      for (int t = 0; t < T; ++t) block_load(t, M, cnt2);
+      for (int t = 0; t < T; ++t) block_load(t, M, cnt2, ld, 0, W->pos);
       for (int t = 0; t < T; ++t) block_store_t(t, W->panel, ld, cnt2);
     }
     for (int b = 0; b < p; ++b) {
@@ -252,7 +253,7 @@ static int lu_w(double* M, const double* J, double gm, int form, int n, int ld, 
       const double* Lt = (g & 1) ? W->U12 : W->panel;
       const int more = b + 1 < p || p + 1 < np;
       if (more)
-        for (int t = 0; t < T; ++t) block_load(t, M + (b + 1 < p ? kb + NB : 0) * ld, cnt2);
+        for (int t = 0; t < T; ++t) block_load(t, M + (b + 1 < p ? kb + NB : 0) * ld, cnt2, ld, b + 1 < p ? kb + NB : 0, W->pos);
       const int zm = W->zpm[b];
       for (int w = 0; w < 4; ++w) apply_block(w, Lt, kb, zm, W);
       if (more)
@@ -275,10 +276,10 @@ static int lu_w(double* M, const double* J, double gm, int form, int n, int ld, 
   return W->ired[15];
 }
 
-/* one block of the substitution: every row's entries in the block's columns
- * (loaded ahead; columns past n - 1 read column n - 1, rows past ld - 1 row
- * 0), the block rows' entries through LDS (the second 12-column buffer) to
- * wave 0, the triangle, then every row */
+/* one block of the substitution: the entries in the block's columns of every
+ * row that takes part (loaded ahead; columns past n - 1 read column n - 1,
+ * other rows read row 0), the block rows' entries through LDS (the second
+ * 12-column buffer) to wave 0, the triangle, then every row */
 static void solve_block(int fwd, int k0, int n, int ld, const double* M, lds_t* W, const int* pt) {
   double* b = W->b;
   double* xb = W->ub;
@@ -286,7 +287,8 @@ static void solve_block(int fwd, int k0, int n, int ld, const double* M, lds_t* 
   const int nb = imin(SB, n - k0);
   static double v[T][SB];
   for (int t = 0; t < T; ++t) {
-    const int r = t < ld ? t : 0;
+    const int need = fwd ? pt[t] >= k0 : (pt[t] >= 0 && pt[t] < k0 + SB);
+    const int r = need ? t : 0;
     for (int j = 0; j < SB; ++j) v[t][j] = M[imin(k0 + j, n - 1) * ld + r];
   }
   for (int t = 0; t < T; ++t) {
