@@ -4,20 +4,20 @@
 // The Jacobian J and the Rosenbrock matrix M = I/(gamma h) - J of a
 // 160-species cell are 161 x 161 FP64 (207 KB each): they fit neither one
 // wave's registers nor the 160 KB LDS of a CU. Each resident workgroup
-// therefore owns a workspace slot in HBM holding J and M (column-major,
-// leading dimension ld); the number of slots, and so of cells in flight, is
-// bounded by the HBM budget. Everything else of the cell (state, stage
-// vectors, concentrations, per-reaction rates) lives in LDS.
+// therefore owns a workspace slot in HBM holding J and the LU factors of M
+// (column-major, leading dimension ld); the number of slots, and so of cells
+// in flight, is bounded by the HBM budget. Everything else of the cell
+// (state, stage vectors, concentrations, per-reaction rates) lives in LDS.
 //
 // The LU is a left-looking blocked getrf that never moves a row in HBM:
 // the row interchanges are kept as a permutation, so physical row q of M
 // stays at offset q of every column. Panel by panel (12 columns), the panel
 // is first brought up to date with every finished column to its left, each
 // wave holding three of its columns in registers while the finished columns
-// stream through LDS twelve at a time; wave 0 then factors the panel in
-// registers and writes it back. Every element sees the same sequence of
-// operations as in an unblocked row-swapping LU, in the same order, so the
-// factors do not depend on the blocking.
+// stream through LDS twelve at a time; the four waves then factor the panel
+// with one row per lane and write it back. Every element sees the same
+// sequence of operations as in an unblocked row-swapping LU, in the same
+// order, so the factors do not depend on the blocking.
 
 #include <cmath>
 #include <cstdint>
@@ -34,13 +34,13 @@ using namespace dev;
 constexpr int kT = kWideThreads;
 constexpr int kNB = kWidePanel;
 
-// Per-cell LDS area. Region A (right-hand-side buffers) and region B (two
-// 12-column buffers of the LU) are never live at the same time and share
+// Per-cell LDS area. Region A (right-hand-side buffers) and region B (the
+// LU's two 12-column buffers) are never live at the same time and share
 // storage; so do the stage input ys and the solve right-hand side v, and the
 // stage derivative fs and the trial state yn.
 struct Wide {
   double *C, *gRT, *hRT, *RB;                   // A: ns, ns, ns, 5 nr
-  double *panel, *U12;                          // B: kNB ld, kNB ld
+  double *buf0, *buf1;                          // B: the LU's two 12-column buffers, kNB ld each
   double *y, *f0, *fs, *ys, *yn, *v, *u[4];     // 8 distinct vectors of ld
   double* red;                                  // 16
   double* ub;                                   // 144: per wave, 12 x 3 values of the LU's U block
@@ -70,8 +70,8 @@ __device__ inline Wide wide_area(double* base, int ns, int nr, int ld) {
   W.gRT = W.C + ns;
   W.hRT = W.gRT + ns;
   W.RB = W.hRT + ns;
-  W.panel = base;
-  W.U12 = base + kNB * ld;
+  W.buf0 = base;
+  W.buf1 = base + kNB * ld;
   double* q = base + wide_region(ns, nr, ld);
   W.y = q;
   W.f0 = q + ld;
@@ -727,7 +727,7 @@ __device__ __forceinline__ int lu_w(double* M, const double* J, double gm, int n
     if (p == 1) {
       // the first finished block, not loaded ahead
       lu_block_load(M, cnt2, 0, mx, R);
-      block_store_t(W.panel, ld, cnt2, R);
+      block_store_t(W.buf0, ld, cnt2, R);
       __syncthreads();
     }
     for (int b = 0; b < p; ++b) {
@@ -736,13 +736,14 @@ __device__ __forceinline__ int lu_w(double* M, const double* J, double gm, int n
       const bool more = b + 1 < p || p + 1 < np;
       if (more) lu_block_load(M + (b + 1 < p ? kb + kNB : 0) * ld, cnt2, b + 1 < p ? kb + kNB : 0, mx, R);
       const int zm = __builtin_amdgcn_readfirstlane(zpm[b]);
-      apply_block(A0, A1, A2, A3, ps, (g & 1) ? W.U12 : W.panel, kb, zm, n, W);
-      if (more) block_store_t((g & 1) ? W.panel : W.U12, ld, cnt2, R);
+      apply_block(A0, A1, A2, A3, ps, (g & 1) ? W.buf1 : W.buf0, kb, zm, n, W);
+      if (more) block_store_t((g & 1) ? W.buf0 : W.buf1, ld, cnt2, R);
       __syncthreads();
       ++g;
     }
-    // the panel to wave 0, as rows of kNB, through the buffer the last block used
-    double* H = (g & 1) ? W.panel : W.U12;
+    // the panel to the factorisation, as rows of kNB, through the buffer the
+    // last block used
+    double* H = (g & 1) ? W.buf0 : W.buf1;
     auto* HL = lds(H);
     each_slot(A0, A1, A2, A3, [&](double (&row)[kCW], const int s) {
       const int q = lane + 64 * s;
@@ -791,7 +792,7 @@ __device__ __forceinline__ void solve_block(int k0, int n, int pt, const double 
   using LD2 = __attribute__((address_space(3))) dv2;
   const int t = threadIdx.x;
   const int nb = min(kSB, n - k0);
-  LD* T = lds(W.U12);                  // the block rows' entries, kSB x kSB
+  LD* T = lds(W.buf1);                  // the block rows' entries, kSB x kSB
   LD* xb = lds(W.ub);                  // the block's solved values
   const int rel = pt - k0;
   if (rel >= 0 && rel < nb) {

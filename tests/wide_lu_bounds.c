@@ -41,7 +41,7 @@
 enum { T = 256, NB = 12, RS = 4, CW = 3, PRE = 6, SB = 16 };
 
 typedef struct {
-  double *panel, *U12, *b, *x, *ub;
+  double *buf0, *buf1, *b, *x, *ub;
   int *piv, *perm, *pos, *ired, *zpm;
 } lds_t;
 
@@ -246,21 +246,21 @@ static int lu_w(double* M, const double* J, double gm, int form, int n, int ld, 
       }
     if (p == 1) {
       for (int t = 0; t < T; ++t) block_load(t, M, cnt2, ld, 0, W->pos);
-      for (int t = 0; t < T; ++t) block_store_t(t, W->panel, ld, cnt2);
+      for (int t = 0; t < T; ++t) block_store_t(t, W->buf0, ld, cnt2);
     }
     for (int b = 0; b < p; ++b) {
       const int kb = b * NB;
-      const double* Lt = (g & 1) ? W->U12 : W->panel;
+      const double* Lt = (g & 1) ? W->buf1 : W->buf0;
       const int more = b + 1 < p || p + 1 < np;
       if (more)
         for (int t = 0; t < T; ++t) block_load(t, M + (b + 1 < p ? kb + NB : 0) * ld, cnt2, ld, b + 1 < p ? kb + NB : 0, W->pos);
       const int zm = W->zpm[b];
       for (int w = 0; w < 4; ++w) apply_block(w, Lt, kb, zm, W);
       if (more)
-        for (int t = 0; t < T; ++t) block_store_t(t, (g & 1) ? W->panel : W->U12, ld, cnt2);
+        for (int t = 0; t < T; ++t) block_store_t(t, (g & 1) ? W->buf0 : W->buf1, ld, cnt2);
       ++g;
     }
-    double* H = (g & 1) ? W->panel : W->U12;
+    double* H = (g & 1) ? W->buf0 : W->buf1;
     for (int t = 0; t < T; ++t) {
       const int lane = t & 63, w = t >> 6;
       for (int s = 0; s < RS; ++s) {
@@ -283,7 +283,7 @@ static int lu_w(double* M, const double* J, double gm, int form, int n, int ld, 
 static void solve_block(int fwd, int k0, int n, int ld, const double* M, lds_t* W, const int* pt) {
   double* b = W->b;
   double* xb = W->ub;
-  double* Tb = W->U12;
+  double* Tb = W->buf1;
   const int nb = imin(SB, n - k0);
   static double v[T][SB];
   for (int t = 0; t < T; ++t) {
@@ -369,8 +369,8 @@ int main(int argc, char** argv) {
     double* M = (double*)malloc(sizeof(double) * (size_t)n * ld);
     double* Ain = (double*)malloc(sizeof(double) * (size_t)n * n);
     lds_t W;
-    W.panel = (double*)malloc(sizeof(double) * (size_t)NB * ld);
-    W.U12 = (double*)malloc(sizeof(double) * (size_t)NB * ld);
+    W.buf0 = (double*)malloc(sizeof(double) * (size_t)NB * ld);
+    W.buf1 = (double*)malloc(sizeof(double) * (size_t)NB * ld);
     W.b = (double*)malloc(sizeof(double) * ld);
     W.x = (double*)malloc(sizeof(double) * ld);
     W.piv = (int*)malloc(sizeof(int) * ld);
@@ -380,7 +380,7 @@ int main(int argc, char** argv) {
     W.zpm = (int*)malloc(sizeof(int) * 32);
     W.ub = (double*)malloc(sizeof(double) * 144);
     /* uninitialised LDS and padding rows hold NaN: they must never be used */
-    for (int i = 0; i < NB * ld; ++i) W.panel[i] = W.U12[i] = NAN;
+    for (int i = 0; i < NB * ld; ++i) W.buf0[i] = W.buf1[i] = NAN;
     for (int i = 0; i < 144; ++i) W.ub[i] = NAN;
     for (size_t i = 0; i < (size_t)n * ld; ++i) M[i] = NAN;
     if (pattern == 1) {
@@ -441,7 +441,7 @@ int main(int argc, char** argv) {
       for (int j = 0; j < n; ++j) fwrite(&M[j * ld + W.perm[i]], sizeof(double), 1, f);
     fwrite(W.piv, sizeof(int), n, f);
     fwrite(W.x, sizeof(double), n, f);
-    free(M); free(J); free(Ain); free(W.panel); free(W.U12); free(W.b); free(W.x);
+    free(M); free(J); free(Ain); free(W.buf0); free(W.buf1); free(W.b); free(W.x);
     free(W.piv); free(W.perm); free(W.pos); free(W.ired); free(W.zpm); free(W.ub);
   }
   fclose(f);
