@@ -33,6 +33,10 @@ using namespace dev;
 
 constexpr int kT = kWideThreads;
 constexpr int kNB = kWidePanel;
+// The LU's blocks sit in LDS as rows of kNB doubles at a stride of kLS: 14
+// rather than 12 spreads the transposed stores of consecutive row pairs over
+// more LDS banks, and keeps every row 16-byte aligned.
+constexpr int kLS = 14;
 
 // Per-cell LDS area. Region A (right-hand-side buffers) and region B (the
 // LU's two 12-column buffers) are never live at the same time and share
@@ -40,7 +44,7 @@ constexpr int kNB = kWidePanel;
 // stage derivative fs and the trial state yn.
 struct Wide {
   double *C, *gRT, *hRT, *RB;                   // A: ns, ns, ns, 5 nr
-  double *buf0, *buf1;                          // B: the LU's two 12-column buffers, kNB ld each
+  double *buf0, *buf1;                          // B: the LU's two 12-column buffers, kLS ld each
   double *y, *f0, *fs, *ys, *yn, *v, *u[4];     // 8 distinct vectors of ld
   double* red;                                  // 16
   double* ub;                                   // 144: per wave, 12 x 3 values of the LU's U block
@@ -54,7 +58,7 @@ struct Wide {
 
 __host__ __device__ inline int wide_region(int ns, int nr, int ld) {
   const int a = 3 * ns + 5 * nr;
-  const int b = 2 * kNB * ld;
+  const int b = 2 * kLS * ld;
   return ((a > b ? a : b) + 1) & ~1;
 }
 
@@ -71,7 +75,7 @@ __device__ inline Wide wide_area(double* base, int ns, int nr, int ld) {
   W.hRT = W.gRT + ns;
   W.RB = W.hRT + ns;
   W.buf0 = base;
-  W.buf1 = base + kNB * ld;
+  W.buf1 = base + kLS * ld;
   double* q = base + wide_region(ns, nr, ld);
   W.y = q;
   W.f0 = q + ld;
@@ -418,7 +422,7 @@ __device__ __forceinline__ void lu_block_load(const double* src, int cnt2, int k
   }
 }
 // the block (column-major, kNB columns of ld) into LDS as rows of kNB:
-// element (row q, column m) at dst[q * kNB + m]
+// element (row q, column m) at dst[q * kLS + m]
 __device__ __forceinline__ void block_store_t(double* dst, int ld, int cnt2, const dv2 (&r)[kPre]) {
   auto* d = lds(dst);
 #pragma unroll
@@ -426,8 +430,8 @@ __device__ __forceinline__ void block_store_t(double* dst, int ld, int cnt2, con
     const int e = static_cast<int>(threadIdx.x) + kT * i;
     if (e < cnt2) {
       const int m = (2 * e) / ld, q = 2 * e - m * ld;   // q even, q + 1 < ld
-      d[q * kNB + m] = r[i].x;
-      d[(q + 1) * kNB + m] = r[i].y;
+      d[q * kLS + m] = r[i].x;
+      d[(q + 1) * kLS + m] = r[i].y;
     }
   }
 }
@@ -485,7 +489,12 @@ __device__ __forceinline__ double row_share(double v, int src) {
     case 7: return row_share_c<7>(v);
     case 8: return row_share_c<8>(v);
     case 9: return row_share_c<9>(v);
-    default: return row_share_c<10>(v);
+    case 10: return row_share_c<10>(v);
+    case 11: return row_share_c<11>(v);
+    case 12: return row_share_c<12>(v);
+    case 13: return row_share_c<13>(v);
+    case 14: return row_share_c<14>(v);
+    default: return row_share_c<15>(v);
   }
 }
 
@@ -517,7 +526,7 @@ __device__ __forceinline__ void apply_block(double (&A0)[kCW], double (&A1)[kCW]
   double lr[kNB];
   {
     const int q = act ? lds(W.perm)[kb + m] : 0;
-    const LD2* r = reinterpret_cast<const LD2*>(Lt + q * kNB);
+    const LD2* r = reinterpret_cast<const LD2*>(Lt + q * kLS);
 #pragma unroll
     for (int j = 0; j < kNB / 2; ++j) {
       const dv2 v = r[j];
@@ -547,7 +556,7 @@ __device__ __forceinline__ void apply_block(double (&A0)[kCW], double (&A1)[kCW]
     const int q = lane + 64 * s;
     const int rel = ps[s] - kb;
     if (rel >= kNB) {
-      const LD2* r = reinterpret_cast<const LD2*>(Lt + q * kNB);
+      const LD2* r = reinterpret_cast<const LD2*>(Lt + q * kLS);
       double l[kNB];
 #pragma unroll
       for (int j = 0; j < kNB / 2; ++j) {
@@ -570,7 +579,7 @@ __device__ __forceinline__ void apply_block(double (&A0)[kCW], double (&A1)[kCW]
 }
 
 // All four waves: factor panel columns k0 .. k0 + nb - 1. The panel arrives in
-// LDS as rows of kNB doubles (H[q * kNB + c], physical row q); lane l of wave
+// LDS as rows of kNB doubles (H[q * kLS + c], physical row q); lane l of wave
 // w holds row q = 64 w + l in registers, rotated so that the current column
 // is always P[0] (the loop over columns then needs no run-time register
 // index). At each column every wave finds its best candidate (DPP
@@ -595,7 +604,7 @@ __device__ __forceinline__ void factor_panel(double* Mg, const double* Hg, int n
   int info = lds(W.ired)[15];
   double P[kNB];
   {
-    const LD2* r = reinterpret_cast<const LD2*>(H + (q < n ? q : 0) * kNB);
+    const LD2* r = reinterpret_cast<const LD2*>(H + (q < n ? q : 0) * kLS);
 #pragma unroll
     for (int j = 0; j < kNB / 2; ++j) {
       const dv2 v = r[j];
@@ -627,19 +636,28 @@ __device__ __forceinline__ void factor_panel(double* Mg, const double* Hg, int n
     }
     __syncthreads();
     // the winner among the four waves' candidates: largest key, then the
-    // smallest code
+    // smallest code (all four slots' key, code and first two row entries
+    // read at once; the choice runs on selects)
     const LD* set = cand + (c & 1) * 4 * kCand;
-    double bk = set[0];
-    int bc = int_of_double(set[1]), bw = 0;
+    dv2 kc[4], a01[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      kc[v] = reinterpret_cast<const LD2*>(set + v * kCand)[0];
+      a01[v] = reinterpret_cast<const LD2*>(set + v * kCand)[1];
+    }
+    double bk = kc[0].x;
+    int bc = int_of_double(kc[0].y), bw = 0;
+    dv2 ba = a01[0];
 #pragma unroll
     for (int v = 1; v < 4; ++v) {
-      const double kv = set[v * kCand];
-      const int cv = int_of_double(set[v * kCand + 1]);
-      if (kv > bk || (kv == bk && cv < bc)) {
-        bk = kv;
-        bc = cv;
-        bw = v;
-      }
+      const double kv = kc[v].x;
+      const int cv = int_of_double(kc[v].y);
+      const bool better = kv > bk || (kv == bk && cv < bc);
+      bk = better ? kv : bk;
+      bc = better ? cv : bc;
+      bw = better ? v : bw;
+      ba.x = better ? a01[v].x : ba.x;
+      ba.y = better ? a01[v].y : ba.y;
     }
     bw = __builtin_amdgcn_readfirstlane(bw);
     const int pv = __builtin_amdgcn_readfirstlane(bc) >> 8, qs = __builtin_amdgcn_readfirstlane(bc) & 255;
@@ -650,10 +668,12 @@ __device__ __forceinline__ void factor_panel(double* Mg, const double* Hg, int n
       pq = pv;
     }
     double pr[kNB];
+    pr[0] = ba.x;
+    pr[1] = ba.y;
     {
       const LD2* r2 = reinterpret_cast<const LD2*>(set + bw * kCand + 2);
 #pragma unroll
-      for (int j = 0; j < kNB / 2; ++j) {
+      for (int j = 1; j < kNB / 2; ++j) {
         const dv2 v = r2[j];
         pr[2 * j] = v.x;
         pr[2 * j + 1] = v.y;
@@ -749,7 +769,7 @@ __device__ __forceinline__ int lu_w(double* M, const double* J, double gm, int n
       const int q = lane + 64 * s;
 #pragma unroll
       for (int cc = 0; cc < kCW; ++cc)
-        if (q < n) HL[q * kNB + kCW * w + cc] = row[cc];
+        if (q < n) HL[q * kLS + kCW * w + cc] = row[cc];
     });
     __syncthreads();
     if (p + 1 < np) load_cols<FORM>(A0, A1, A2, A3, FORM ? J : M, gm, n, ld, k0 + kNB, min(kNB, n - k0 - kNB));
@@ -767,9 +787,9 @@ __device__ __forceinline__ int lu_w(double* M, const double* J, double gm, int n
 // in the block's columns, two blocks ahead (three register sets, loads
 // issued unconditionally so that each wait is for one set only). The rows
 // inside the block hand theirs to wave 0 through LDS; wave 0 solves the
-// block's triangle, the solved value of each step broadcast by readlane (the
-// backward steps multiply by the diagonal's reciprocal); every thread then
-// updates its row.
+// block's triangle on lanes 0..15, the solved value of each step broadcast
+// along them by DPP (row_newbcast; the backward steps multiply by the
+// diagonal's reciprocal); every thread then updates its row.
 constexpr int kSB = 16;
 
 // row t's entries in columns k0 .. k0 + kSB - 1 when the row takes part in
@@ -814,28 +834,33 @@ __device__ __forceinline__ void solve_block(int k0, int n, int pt, const double 
       }
     }
     double xv = t < nb ? b[r] : 0.0;
+    // the multipliers are masked rather than the updates, which keeps the
+    // selects off the chain of dependent broadcasts (a zero multiplier
+    // leaves xv unchanged for finite z)
     if (FWD) {
 #pragma unroll
       for (int j = 0; j + 1 < kSB; ++j) {
         if (j + 1 < nb) {
-          const double z = rl_d(xv, j);
-          if (t > j && t < nb) xv = xv - lc[j] * z;
+          const double lm = (t > j && t < nb) ? lc[j] : 0.0;
+          const double z = row_share(xv, j);
+          xv = xv - lm * z;
         }
       }
     } else {
-      // the diagonal's reciprocals, all lanes at once
+      // the diagonal's reciprocals, all lanes at once; lane j's value is
+      // final once the steps above it are done (its multipliers from then
+      // on are zero), and is scaled by its reciprocal when broadcast and at
+      // the end
       const double rdg = 1.0 / (t < nb ? T[t * kSB + t] : 1.0);
 #pragma unroll
       for (int j = kSB - 1; j >= 0; --j) {
         if (j < nb) {
-          const double z = rl_d(xv, j) * rl_d(rdg, j);
-          if (t == j) {
-            xv = z;
-          } else if (t < j) {
-            xv = xv - lc[j] * z;
-          }
+          const double lm = t < j ? lc[j] : 0.0;
+          const double z = row_share(xv * rdg, j);
+          xv = xv - lm * z;
         }
       }
+      xv = xv * rdg;
     }
     if (t < nb) {
       b[r] = xv;

@@ -5,8 +5,8 @@
  *
  * Every buffer the kernel touches is allocated on its own, at exactly the
  * size the kernel's layout gives it: in LDS the two 12-column buffers
- * (kNB ld doubles each, one block of multipliers as rows of 12, or the panel
- * as rows of 12), the waves' U-block tables (4 x 36 doubles), piv, perm and
+ * (kLS ld doubles each, one block of multipliers as rows of 12 at a stride
+ * of 14, or the panel likewise), the waves' U-block tables (4 x 36 doubles), piv, perm and
  * pos (ld ints each), the reduction scratch (16 ints), the zero-pivot masks
  * (32 ints) and the solve vectors (ld doubles each); in HBM the matrix slot (n
  * columns of ld doubles). An access outside any of them stops the program
@@ -38,7 +38,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { T = 256, NB = 12, RS = 4, CW = 3, PRE = 6, SB = 16 };
+enum { T = 256, NB = 12, LS = 14, RS = 4, CW = 3, PRE = 6, SB = 16 };
 
 typedef struct {
   double *buf0, *buf1, *b, *x, *ub;
@@ -69,8 +69,8 @@ static void block_store_t(int t, double* dst, int ld, int cnt2) {
     const int e = t + T * i;
     if (e < cnt2) {
       const int m = (2 * e) / ld, q = 2 * e - m * ld;
-      dst[q * NB + m] = R[t][i][0];
-      dst[(q + 1) * NB + m] = R[t][i][1];
+      dst[q * LS + m] = R[t][i][0];
+      dst[(q + 1) * LS + m] = R[t][i][1];
     }
   }
 }
@@ -107,7 +107,7 @@ static void apply_block(int w, const double* Lt, int kb, int zm, lds_t* W) {
     const int act = cc < CW && m < NB;
     x[lane] = act ? Tw[m * CW + cc] : 0.0;
     const int q = act ? W->perm[kb + m] : 0;
-    for (int j = 0; j < NB; ++j) lr[lane][j] = Lt[q * NB + j];
+    for (int j = 0; j < NB; ++j) lr[lane][j] = Lt[q * LS + j];
   }
   for (int j = 0; j + 1 < NB; ++j) {
     if ((zm >> j) & 1) continue;
@@ -132,7 +132,7 @@ static void apply_block(int w, const double* Lt, int kb, int zm, lds_t* W) {
       const int rel = PS[t][s] - kb;
       if (rel >= NB) {
         double l[NB];
-        for (int j = 0; j < NB; ++j) l[j] = Lt[q * NB + j];
+        for (int j = 0; j < NB; ++j) l[j] = Lt[q * LS + j];
         for (int j = 0; j < NB; ++j) {
           if ((zm >> j) & 1) continue;
           for (int c = 0; c < CW; ++c) A[t][s][c] = A[t][s][c] - l[j] * U[j][c];
@@ -153,7 +153,7 @@ static void factor_panel(double* M, const double* H, int n, int ld, int k0, int 
   double* cand = W->ub;
   for (int t = 0; t < T; ++t) {
     pq[t] = t < n ? W->pos[t] : -1;
-    for (int j = 0; j < NB; ++j) P[t][j] = t < n ? H[t * NB + j] : 0.0;
+    for (int j = 0; j < NB; ++j) P[t][j] = t < n ? H[t * LS + j] : 0.0;
   }
   for (int c = 0; c < nb; ++c) {
     const int k = k0 + c;
@@ -266,7 +266,7 @@ static int lu_w(double* M, const double* J, double gm, int form, int n, int ld, 
       for (int s = 0; s < RS; ++s) {
         const int q = lane + 64 * s;
         for (int cc = 0; cc < CW; ++cc)
-          if (q < n) H[q * NB + CW * w + cc] = A[t][s][cc];
+          if (q < n) H[q * LS + CW * w + cc] = A[t][s][cc];
       }
     }
     if (p + 1 < np)
@@ -304,22 +304,29 @@ static void solve_block(int fwd, int k0, int n, int ld, const double* M, lds_t* 
     xv[t] = t < nb ? b[r[t]] : 0.0;
     rdg[t] = fwd ? 0.0 : 1.0 / (t < nb ? Tb[t * SB + t] : 1.0);
   }
+  /* each step: the value of lane j of every 16-lane row (a DPP broadcast,
+   * read by all lanes before any writes), times a multiplier that is zero
+   * outside the rows it updates */
+  double z[64];
   if (fwd) {
     for (int j = 0; j + 1 < SB; ++j)
       if (j + 1 < nb) {
-        const double z = xv[j];
-        for (int t = 0; t < 64; ++t)
-          if (t > j && t < nb) xv[t] = xv[t] - lc[t][j] * z;
+        for (int t = 0; t < 64; ++t) z[t] = xv[16 * (t / 16) + j];
+        for (int t = 0; t < 64; ++t) {
+          const double lm = (t > j && t < nb) ? lc[t][j] : 0.0;
+          xv[t] = xv[t] - lm * z[t];
+        }
       }
   } else {
     for (int j = SB - 1; j >= 0; --j)
       if (j < nb) {
-        const double z = xv[j] * rdg[j];
+        for (int t = 0; t < 64; ++t) z[t] = xv[16 * (t / 16) + j] * rdg[16 * (t / 16) + j];
         for (int t = 0; t < 64; ++t) {
-          if (t == j) xv[t] = z;
-          else if (t < j) xv[t] = xv[t] - lc[t][j] * z;
+          const double lm = t < j ? lc[t][j] : 0.0;
+          xv[t] = xv[t] - lm * z[t];
         }
       }
+    for (int t = 0; t < 64; ++t) xv[t] = xv[t] * rdg[t];
   }
   for (int t = 0; t < 64; ++t)
     if (t < nb) {
@@ -369,8 +376,8 @@ int main(int argc, char** argv) {
     double* M = (double*)malloc(sizeof(double) * (size_t)n * ld);
     double* Ain = (double*)malloc(sizeof(double) * (size_t)n * n);
     lds_t W;
-    W.buf0 = (double*)malloc(sizeof(double) * (size_t)NB * ld);
-    W.buf1 = (double*)malloc(sizeof(double) * (size_t)NB * ld);
+    W.buf0 = (double*)malloc(sizeof(double) * (size_t)LS * ld);
+    W.buf1 = (double*)malloc(sizeof(double) * (size_t)LS * ld);
     W.b = (double*)malloc(sizeof(double) * ld);
     W.x = (double*)malloc(sizeof(double) * ld);
     W.piv = (int*)malloc(sizeof(int) * ld);
@@ -380,7 +387,7 @@ int main(int argc, char** argv) {
     W.zpm = (int*)malloc(sizeof(int) * 32);
     W.ub = (double*)malloc(sizeof(double) * 144);
     /* uninitialised LDS and padding rows hold NaN: they must never be used */
-    for (int i = 0; i < NB * ld; ++i) W.buf0[i] = W.buf1[i] = NAN;
+    for (int i = 0; i < LS * ld; ++i) W.buf0[i] = W.buf1[i] = NAN;
     for (int i = 0; i < 144; ++i) W.ub[i] = NAN;
     for (size_t i = 0; i < (size_t)n * ld; ++i) M[i] = NAN;
     if (pattern == 1) {
