@@ -209,6 +209,28 @@ int chem_integrate_steps(chem_solver* s, int32_t n_steps, int64_t n_cells, doubl
                          const double* phi_in, double* phi_out, double* h_io, int32_t* n_acc,
                          int32_t* n_rej, int8_t* status, void* stream);
 
+/* Paper: Methodology (the ODE solver's cost per cell is what the load
+ * balancing distributes; Fig. 2 separates the Jacobian's share of it).
+ * Per-cell counts of evaluations, written by every later integration call of
+ * this solver (chem_integrate, chem_integrate_noalloc, chem_integrate_steps
+ * and chem_integrate_zonal) next to n_acc and n_rej:
+ *   n_jac : device [n_cells] int32 or NULL: Jacobian evaluations (analytical,
+ *           or one forward-difference Jacobian), one per step start: once at
+ *           the start and after every accepted step that the integration
+ *           continues from;
+ *   n_fev : device [n_cells] int32 or NULL: evaluations of the right-hand
+ *           side f: one per step start, the n more that a forward-difference
+ *           Jacobian makes, and the stages of every attempt whose LU
+ *           succeeded that need f at a new point (two per attempt for Rodas3
+ *           and for ROS4).
+ * Both arrays must hold n_cells entries for every later call, stay valid
+ * while calls use them, and are overwritten per call (chem_integrate_steps
+ * adds over its steps; cells that chem_integrate_zonal maps get 0). Pass NULL
+ * for both to stop. The pointers are kept, not owned; a cached graph of
+ * chained steps is dropped so that the next chem_integrate_steps captures
+ * them. Errors: CHEM_EINVAL (s NULL). */
+int chem_eval_counters(chem_solver* s, int32_t* n_jac, int32_t* n_fev);
+
 /* ---- kernel-level entry points (tests and roofline measurements) -------- */
 
 /* Paper: Methodology, Analytical Jacobian paragraph: the right-hand side

@@ -581,12 +581,15 @@ typedef struct {
   const orc_mech* m;
   int red;               /* 1: bath gas (last species) dropped */
   double *yfull, *ffull, *Jfull;
+  long nfev, njac;       /* evaluations of f and of J (analytical or by differences) */
 } model_t;
 
 static void model_init(model_t* mo, const orc_mech* m, int red) {
   int nf = m->ns + 1;
   mo->m = m;
   mo->red = red;
+  mo->nfev = 0;
+  mo->njac = 0;
   mo->yfull = (double*)calloc((size_t)nf * (nf + 2), sizeof(double));
   mo->ffull = mo->yfull + nf;
   mo->Jfull = mo->ffull + nf;
@@ -605,6 +608,7 @@ static void model_full(const model_t* mo, const double* y, double* yf) {
 }
 
 static void model_rhs(model_t* mo, double p, const double* y, double* f) {
+  mo->nfev++;
   if (!mo->red) { orc_rhs(mo->m, p, y, f); return; }
   int ns = mo->m->ns;
   model_full(mo, y, mo->yfull);
@@ -613,6 +617,7 @@ static void model_rhs(model_t* mo, double p, const double* y, double* f) {
 }
 
 static void model_jac(model_t* mo, double p, const double* y, double* J) {
+  mo->njac++;
   if (!mo->red) { orc_jac(mo->m, p, y, J); return; }
   int ns = mo->m->ns, nf = ns + 1;
   model_full(mo, y, mo->yfull);
@@ -626,6 +631,7 @@ static void model_jac(model_t* mo, double p, const double* y, double* J) {
 /* forward differences of the integrated f (same increment rule as orc_jac_fd) */
 static void model_jac_fd(model_t* mo, double p, const double* y, const double* f0, double* J) {
   int n = model_n(mo);
+  mo->njac++;
   double* yp = (double*)malloc(sizeof(double) * 2 * n);
   double* fp = yp + n;
   for (int j = 0; j < n; ++j) {
@@ -830,6 +836,8 @@ static int integrate_cell(model_t* mo, double p, double dt, const orc_opts* o, d
                           double* h_io, int* nacc_out, int* nrej_out, work_t* w, double* y_new,
                           double* err_vec) {
   int n = model_n(mo);
+  mo->nfev = 0;
+  mo->njac = 0;
   const tableau_t* tb = tableau_of(o->scheme);
   int nacc = 0, nrej = 0, attempts = 0, status = ORC_OK;
   for (int i = 0; i < n; ++i) if (!isfinite(y[i])) status = ORC_NONFINITE;
@@ -912,6 +920,7 @@ typedef struct {
   double* out;
   double* h_io;
   int *nacc, *nrej;
+  int *njac, *nfev;
   signed char* status;
   atomic_long next;
 } job_t;
@@ -950,6 +959,8 @@ static void* worker(void* arg) {
     if (jb->h_io) jb->h_io[c] = h;
     if (jb->nacc) jb->nacc[c] = na;
     if (jb->nrej) jb->nrej[c] = nr;
+    if (jb->njac) jb->njac[c] = (int)mo.njac;
+    if (jb->nfev) jb->nfev[c] = (int)mo.nfev;
     if (jb->status) jb->status[c] = (signed char)st;
   }
   free(y);
@@ -961,6 +972,12 @@ static void* worker(void* arg) {
 int orc_integrate(const orc_mech* m, long n_cells, double dt, const orc_opts* o,
                   const double* phi_in, double* phi_out, double* h_io, int* n_acc, int* n_rej,
                   signed char* status, int n_threads) {
+  return orc_integrate_counts(m, n_cells, dt, o, phi_in, phi_out, h_io, n_acc, n_rej, NULL, NULL, status, n_threads);
+}
+
+int orc_integrate_counts(const orc_mech* m, long n_cells, double dt, const orc_opts* o,
+                         const double* phi_in, double* phi_out, double* h_io, int* n_acc, int* n_rej,
+                         int* n_jac, int* n_fev, signed char* status, int n_threads) {
   if (!m || !o || n_cells < 0 || !(dt > 0.0) || (n_cells > 0 && (!phi_in || !phi_out)) || !tableau_of(o->scheme) ||
       (o->jacobian != ORC_JAC_ANALYTICAL && o->jacobian != ORC_JAC_FD) ||
       (o->state != ORC_STATE_FULL && o->state != ORC_STATE_NO_BATH) || (o->state == ORC_STATE_NO_BATH && m->ns < 2)) {
@@ -971,6 +988,7 @@ int orc_integrate(const orc_mech* m, long n_cells, double dt, const orc_opts* o,
   job_t jb;
   jb.m = m; jb.n_cells = n_cells; jb.dt = dt; jb.o = o; jb.in = phi_in; jb.out = phi_out;
   jb.h_io = h_io; jb.nacc = n_acc; jb.nrej = n_rej; jb.status = status;
+  jb.njac = n_jac; jb.nfev = n_fev;
   atomic_init(&jb.next, 0);
   if (n_threads < 1) n_threads = 1;
   if (n_threads == 1) { worker(&jb); return 0; }

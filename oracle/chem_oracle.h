@@ -116,6 +116,15 @@ int orc_integrate(const orc_mech* m, long n_cells, double dt, const orc_opts* o,
                   const double* phi_in, double* phi_out, double* h_io, int* n_acc, int* n_rej,
                   signed char* status, int n_threads);
 
+/* The same, also counting for every cell the evaluations of the Jacobian
+ * (n_jac: analytical, or one forward-difference Jacobian) and of the
+ * right-hand side f (n_fev: every call of f, including the n calls a
+ * forward-difference Jacobian makes), counted where they are made. Either
+ * may be NULL. */
+int orc_integrate_counts(const orc_mech* m, long n_cells, double dt, const orc_opts* o,
+                         const double* phi_in, double* phi_out, double* h_io, int* n_acc, int* n_rej,
+                         int* n_jac, int* n_fev, signed char* status, int n_threads);
+
 /* Zonal reference mapping (paper: Methodology, the DLBFoam paragraph): a cell
  * is either integrated or takes the solution of a reference cell with a
  * similar Bilger mixture fraction Z.

@@ -73,6 +73,9 @@ def lib():
         L.orc_integrate.argtypes = [ctypes.c_void_p, ctypes.c_long, ctypes.c_double,
                                     ctypes.POINTER(_Opts), _dp, _dp, _dp, _ip, _ip,
                                     ctypes.POINTER(ctypes.c_byte), ctypes.c_int]
+        L.orc_integrate_counts.argtypes = [ctypes.c_void_p, ctypes.c_long, ctypes.c_double,
+                                           ctypes.POINTER(_Opts), _dp, _dp, _dp, _ip, _ip, _ip, _ip,
+                                           ctypes.POINTER(ctypes.c_byte), ctypes.c_int]
         L.orc_mech_elements.argtypes = [ctypes.c_void_p, _ip, _ip]
         L.orc_mixture_fraction.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, ctypes.c_long, _dp, _dp]
         _lib = L
@@ -181,7 +184,10 @@ class Mech:
 
     def integrate(self, phi, dt: float, rtol=1e-6, atol=1e-10, max_steps=100000, h_io=None,
                   n_threads: int = 1, scheme: int = RODAS3, jacobian: int = JAC_ANALYTICAL,
-                  state: int = STATE_FULL):
+                  state: int = STATE_FULL, counts: bool = False):
+        """(phi_out, h, n_acc, n_rej, status); with counts also the per-cell
+        evaluations of the Jacobian and of f (n_jac, n_fev), counted where
+        they are made."""
         phi = np.ascontiguousarray(phi, dtype=np.float64)
         n_cells = phi.shape[0]
         assert phi.shape[1] == self.ns + 2
@@ -190,13 +196,15 @@ class Mech:
         na = np.zeros(n_cells, dtype=np.int32)
         nr = np.zeros(n_cells, dtype=np.int32)
         st = np.zeros(n_cells, dtype=np.int8)
+        nj = np.zeros(n_cells, dtype=np.int32)
+        nf = np.zeros(n_cells, dtype=np.int32)
         o = _Opts(rtol, atol, max_steps, scheme, jacobian, state)
-        rc = lib().orc_integrate(self._h, n_cells, float(dt), ctypes.byref(o), _d(phi), _d(out), _d(h),
-                                 _i(na), _i(nr), st.ctypes.data_as(ctypes.POINTER(ctypes.c_byte)),
-                                 int(n_threads))
+        rc = lib().orc_integrate_counts(self._h, n_cells, float(dt), ctypes.byref(o), _d(phi), _d(out), _d(h),
+                                        _i(na), _i(nr), _i(nj), _i(nf),
+                                        st.ctypes.data_as(ctypes.POINTER(ctypes.c_byte)), int(n_threads))
         if rc != 0:
             raise ValueError(lib().orc_last_error().decode())
-        return out, h, na, nr, st
+        return (out, h, na, nr, st, nj, nf) if counts else (out, h, na, nr, st)
 
     def elements(self):
         """Atom counts [Ns, Ne] of every species."""

@@ -111,6 +111,8 @@ struct chem_solver {
   double* d_nasa = nullptr;
   double* d_W = nullptr;
   unsigned long long* d_head = nullptr;   // [0] queue head, [1] log head
+  int32_t* d_njac = nullptr;              // caller's per-cell evaluation counters (chem_eval_counters)
+  int32_t* d_nfev = nullptr;
   unsigned char* scratch = nullptr;       // this device's address of the static scratch array
   chemk::Variant variants[8];
   int nvariants = 0;
@@ -496,6 +498,8 @@ int launch_step(chem_solver* s, const chem_opts& o, int64_t n, double dt, const 
   a.n_acc = n_acc;
   a.n_rej = n_rej;
   a.status = reinterpret_cast<signed char*>(status);
+  a.n_jac = s->d_njac;
+  a.n_fev = s->d_nfev;
   a.accumulate = accumulate;
   a.cell_doubles = chemk::cell_doubles(sh.v.nn, s->nr, s->ns);
   a.wpb = sh.wpb;
@@ -1090,6 +1094,15 @@ int chem_workspace_info(chem_solver* s, int32_t* slots, int64_t* bytes_per_slot)
 
 // ---- kernel timing -----------------------------------------------------------
 
+int chem_eval_counters(chem_solver* s, int32_t* n_jac, int32_t* n_fev) {
+  if (!s) return fail(CHEM_EINVAL, "chem_eval_counters: bad argument");
+  DeviceGuard g(s->dev);
+  s->d_njac = n_jac;
+  s->d_nfev = n_fev;
+  drop_graph(s);   // a cached chain of steps holds the previous pointers
+  return CHEM_OK;
+}
+
 int chem_kernel_timing(chem_solver* s, int32_t enable) {
   if (!s) return fail(CHEM_EINVAL, "chem_kernel_timing: bad argument");
   DeviceGuard g(s->dev);
@@ -1255,6 +1268,8 @@ int chem_integrate_zonal(chem_solver* s, int64_t n, double dt, const double* in,
   z.n_acc = n_acc;
   z.n_rej = n_rej;
   z.status = reinterpret_cast<signed char*>(status);
+  z.n_jac = s->d_njac;
+  z.n_fev = s->d_nfev;
   HIP_TRY(chemz::launch_zone_classify(z, st), "zone classify launch");
   HIP_TRY(chemz::launch_zone_select(z, st), "zone select launch");
   chem_opts o = s->opts;

@@ -682,7 +682,8 @@ struct Cell {
   template <int SCHEME, bool GEN>
   __device__ static __forceinline__ void integrate(const MechArgs& A, const MechLds& L, const CellArea& ca,
                                                    const OptsDev& o, double p, double dt, double& y,
-                                                   double& hio, int& nacc_o, int& nrej_o, int& status_o) {
+                                                   double& hio, int& nacc_o, int& nrej_o, int& status_o,
+                                                   int& njac_o, int& nfev_o) {
     using TB = Tab<SCHEME>;
     const int ns = A.ns;
     const bool nb = GEN && o.no_bath != 0;   // bath gas (lane ns) derived, not integrated
@@ -699,6 +700,7 @@ struct Cell {
     double h = hio > 0.0 ? hio : dt;
     double hnext = h, t = 0.0;
     int nacc = 0, nrej = 0, att = 0, consec = 0;
+    int njac = 0, nfev = 0;     // evaluations of J and of f (a difference Jacobian's included)
     bool need = true;
     double f0 = 0.0;
     while (status == 0 && t < dt) {
@@ -715,6 +717,8 @@ struct Cell {
           if (nb) reduce_bath(ca, ns);
         }
         need = false;
+        ++njac;
+        nfev += (GEN && o.jac_fd) ? 1 + n : 1;
       }
       const double rem = dt - t;
       double hc = h;
@@ -756,6 +760,7 @@ struct Cell {
           if (st > 2) ys = ys + tab_a<SCHEME>(st, 2) * u3;
           if (nb) ys = with_bath(ns, ys);
           fs = rhs<false>(A, L, ca, p, ys);
+          ++nfev;
         } else if (src == kFy) {
           fs = f0;
         }
@@ -819,6 +824,8 @@ struct Cell {
     nacc_o = nacc;
     nrej_o = nrej;
     status_o = status;
+    njac_o = njac;
+    nfev_o = nfev;
   }
 };
 
@@ -852,8 +859,8 @@ __device__ __forceinline__ void run_cell(const IntegrateArgs& a, const MechLds& 
   float ft[4];
   if (a.log.cap > 0) cell_features<G>(ns, y, p, a.dt, ft);
   double h = a.h_io ? a.h_io[cell] : 0.0;
-  int nacc, nrej, st;
-  C::template integrate<SCHEME, GEN>(a.m, L, ca, a.o, p, a.dt, y, h, nacc, nrej, st);
+  int nacc, nrej, st, njac, nfev;
+  C::template integrate<SCHEME, GEN>(a.m, L, ca, a.o, p, a.dt, y, h, nacc, nrej, st, njac, nfev);
   double* pout = a.phi_out + cell * w2;
   if (i == 0) {
     pout[0] = y;
@@ -867,10 +874,14 @@ __device__ __forceinline__ void run_cell(const IntegrateArgs& a, const MechLds& 
       if (a.n_acc) a.n_acc[cell] += nacc;
       if (a.n_rej) a.n_rej[cell] += nrej;
       if (a.status && a.status[cell] == 0) a.status[cell] = static_cast<signed char>(st);
+      if (a.n_jac) a.n_jac[cell] += njac;
+      if (a.n_fev) a.n_fev[cell] += nfev;
     } else {
       if (a.n_acc) a.n_acc[cell] = nacc;
       if (a.n_rej) a.n_rej[cell] = nrej;
       if (a.status) a.status[cell] = static_cast<signed char>(st);
+      if (a.n_jac) a.n_jac[cell] = njac;
+      if (a.n_fev) a.n_fev[cell] = nfev;
     }
     if (a.log.cap > 0) {
       const unsigned long long k = atomicAdd(a.log.head, 1ull) % static_cast<unsigned long long>(a.log.cap);

@@ -944,7 +944,7 @@ __device__ void reduce_bath_w(double* J, int ns, int ld) {
 template <int SCHEME, bool GEN>
 __device__ __forceinline__ void integrate_w(const MechArgs& A, const MechLds& L, const Wide& W, double* J, double* M, int ld,
                             const OptsDev& o, double p, double dt, double& hio, int& nacc_o, int& nrej_o,
-                            int& status_o) {
+                            int& status_o, int& njac_o, int& nfev_o) {
   using TB = Tab<SCHEME>;
   const int ns = A.ns;
   const int n = ns + 1;                 // size of J and M
@@ -958,6 +958,7 @@ __device__ __forceinline__ void integrate_w(const MechArgs& A, const MechLds& L,
   double h = hio > 0.0 ? hio : dt;
   double hnext = h, tt = 0.0;
   int nacc = 0, nrej = 0, att = 0, consec = 0;
+  int njac = 0, nfev = 0;     // evaluations of J and of f (a difference Jacobian's included)
   bool need = true;
   while (status == 0 && tt < dt) {
     if (att >= o.max_steps) {
@@ -988,6 +989,8 @@ __device__ __forceinline__ void integrate_w(const MechArgs& A, const MechLds& L,
         if (nb) reduce_bath_w(J, ns, ld);
       }
       need = false;
+      ++njac;
+      nfev += (GEN && o.jac_fd) ? 1 + ni : 1;
     }
     const double rem = dt - tt;
     double hc = h;
@@ -1023,6 +1026,7 @@ __device__ __forceinline__ void integrate_w(const MechArgs& A, const MechLds& L,
         __syncthreads();
         if (nb) with_bath_w(W.ys, ns, W.red);
         rhs_w<false>(A, L, W, p, W.ys, W.fs, nullptr, ld);
+        ++nfev;
       }
       if (t < n) {
         double v = src == kFy ? W.f0[t] : W.fs[t];
@@ -1084,6 +1088,8 @@ __device__ __forceinline__ void integrate_w(const MechArgs& A, const MechLds& L,
   nacc_o = nacc;
   nrej_o = nrej;
   status_o = status;
+  njac_o = njac;
+  nfev_o = nfev;
 }
 
 template <int SCHEME, bool GEN>
@@ -1105,8 +1111,8 @@ __device__ __forceinline__ void run_cell_w(const IntegrateArgs& a, const MechLds
     ft[3] = static_cast<float>(log10(a.dt / 1e-6));
   }
   double h = a.h_io ? a.h_io[cell] : 0.0;
-  int nacc, nrej, st;
-  integrate_w<SCHEME, GEN>(a.m, L, W, J, M, a.ld, a.o, p, a.dt, h, nacc, nrej, st);
+  int nacc, nrej, st, njac, nfev;
+  integrate_w<SCHEME, GEN>(a.m, L, W, J, M, a.ld, a.o, p, a.dt, h, nacc, nrej, st, njac, nfev);
   double* pout = a.phi_out + cell * w2;
   if (t < n) pout[t == 0 ? 0 : 1 + t] = W.y[t];
   if (t == 0) {
@@ -1116,10 +1122,14 @@ __device__ __forceinline__ void run_cell_w(const IntegrateArgs& a, const MechLds
       if (a.n_acc) a.n_acc[cell] += nacc;
       if (a.n_rej) a.n_rej[cell] += nrej;
       if (a.status && a.status[cell] == 0) a.status[cell] = static_cast<signed char>(st);
+      if (a.n_jac) a.n_jac[cell] += njac;
+      if (a.n_fev) a.n_fev[cell] += nfev;
     } else {
       if (a.n_acc) a.n_acc[cell] = nacc;
       if (a.n_rej) a.n_rej[cell] = nrej;
       if (a.status) a.status[cell] = static_cast<signed char>(st);
+      if (a.n_jac) a.n_jac[cell] = njac;
+      if (a.n_fev) a.n_fev[cell] = nfev;
     }
     if (a.log.cap > 0) {
       const unsigned long long k = atomicAdd(a.log.head, 1ull) % static_cast<unsigned long long>(a.log.cap);

@@ -46,6 +46,8 @@ struct IntegrateArgs {
   int* n_acc;
   int* n_rej;
   signed char* status;
+  int* n_jac;                   // evaluations of J per cell, or NULL
+  int* n_fev;                   // evaluations of f per cell, or NULL
   int accumulate;               // add counters / keep first failure status
   int cell_doubles;             // per-cell LDS area (doubles)
   int wpb;                      // waves per block

@@ -193,6 +193,8 @@ __global__ void k_zone_apply(ZoneArgs a) {
     if (k == 0) {
       if (a.n_acc) a.n_acc[c] = 0;
       if (a.n_rej) a.n_rej[c] = 0;
+      if (a.n_jac) a.n_jac[c] = 0;
+      if (a.n_fev) a.n_fev[c] = 0;
       if (a.status) a.status[c] = a.status[ref];
     }
   }

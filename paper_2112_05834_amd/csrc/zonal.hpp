@@ -27,6 +27,8 @@ struct ZoneArgs {
   int* n_acc;                  // the caller's counters and status (NULL allowed)
   int* n_rej;
   signed char* status;
+  int* n_jac;                  // the solver's evaluation counters (NULL allowed)
+  int* n_fev;
 };
 
 // coef[i] = (sum_e coupling[e] counts[i][e]) / W[i]; streams = (beta(y_fuel),

@@ -871,3 +871,46 @@ def test_no_bath_integration_matches_full_state(mech_dir):
     assert np.array_equal(c[0], b[0]) and np.array_equal(c[2], b[2])
     with pytest.raises(ValueError):
         M.integrate(phi[:2], wl.dt, state=2)
+
+
+# ------------------------------------------- evaluation counters (a8) ---
+# njac counts step starts (the first state and every state an accepted step
+# leads to that the integration continues from), nfev adds the new-point
+# stages of every attempt whose LU succeeded (two for Rodas3: stages 3 and 4;
+# two for ROS4, whose stage 4 reuses stage 3's point) and the n evaluations
+# of a forward-difference Jacobian. Pinned here by the step sequence alone.
+
+def test_eval_counts_follow_the_step_sequence(mech_dir):
+    wl, mech, path, phi = synth.workload_inputs("tiny9_1024", mech_dir, n_cells=64)
+    M = O.Mech(path)
+    n = mech.n_species + 1
+    for scheme in (O.RODAS3, O.ROS4):
+        out, h, na, nr, st, nj, nf = M.integrate(phi, wl.dt, scheme=scheme, counts=True)
+        assert (st == 0).all() and (na >= 1).all()
+        assert np.array_equal(nj, na)                      # one Jacobian per accepted step's start state
+        assert np.array_equal(nf, nj + 2 * (na + nr))
+        # the same run without counting gives the same results
+        out2, h2, na2, nr2, st2 = M.integrate(phi, wl.dt, scheme=scheme)
+        assert np.array_equal(out, out2) and np.array_equal(na, na2)
+    out, h, na, nr, st, nj, nf = M.integrate(phi, wl.dt, jacobian=O.JAC_FD, counts=True)
+    assert np.array_equal(nj, na) and np.array_equal(nf, nj * (1 + n) + 2 * (na + nr))
+    out, h, na, nr, st, nj, nf = M.integrate(phi, wl.dt, jacobian=O.JAC_FD, state=O.STATE_NO_BATH, counts=True)
+    assert np.array_equal(nf, nj * (1 + (n - 1)) + 2 * (na + nr))
+
+
+def test_eval_counts_at_failures(mech_dir):
+    wl, mech, path, phi = synth.workload_inputs("tiny9_1024", mech_dir, n_cells=8)
+    M = O.Mech(path)
+    # step underflow: every attempt from the first state, one Jacobian
+    out, h, na, nr, st, nj, nf = M.integrate(phi, wl.dt, rtol=1e-30, atol=1e-300, counts=True)
+    assert (st == 2).all() and (na == 0).all() and (nj == 1).all()
+    assert np.array_equal(nf, 1 + 2 * nr)
+    # one attempt allowed: one start; a cell that needs more stops before
+    # evaluating the next state's Jacobian
+    out, h, na, nr, st, nj, nf = M.integrate(phi, wl.dt, max_steps=1, counts=True)
+    assert (na + nr == 1).all() and (nj == 1).all() and (nf == 3).all()
+    # a non-finite input is not integrated
+    bad = phi.copy()
+    bad[:, 3] = np.nan
+    out, h, na, nr, st, nj, nf = M.integrate(bad, wl.dt, counts=True)
+    assert (st == 3).all() and (nj == 0).all() and (nf == 0).all()
