@@ -329,7 +329,7 @@ def main():
     args = ap.parse_args()
     TOL.update(rtol=args.rtol, atol=args.atol)
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+        print("bench.py: runs on one GPU only; --gpus %d is not supported "
               "(cells are independent: a multi-GPU run would give each GPU its own share of the cells)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
