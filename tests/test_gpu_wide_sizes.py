@@ -3,7 +3,7 @@ on the GPU through the C ABI, against the CPU oracle.
 
 The sizes cover every count of row slots per lane (a lane holds physical rows
 l + 64 s: two slots up to n = 128, three up to 192, four up to 256), the
-largest size, and LU tail panels of width 1, 4, 5, 8 and a full 12:
+largest size, and LU tail panels of width 1, 4, 5, 8, 9 and a full 12:
 
   n =  65  two slots, tail 5          n = 192  three slots, full last panel
   n =  97  tail 1                     n = 193  four slots, tail 1
