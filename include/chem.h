@@ -223,13 +223,15 @@ int chem_integrate_steps(chem_solver* s, int32_t n_steps, int64_t n_cells, doubl
  *           Jacobian makes, and the stages of every attempt whose LU
  *           succeeded that need f at a new point (two per attempt for Rodas3
  *           and for ROS4).
- * Both arrays must hold n_cells entries for every later call, stay valid
- * while calls use them, and are overwritten per call (chem_integrate_steps
- * adds over its steps; cells that chem_integrate_zonal maps get 0). Pass NULL
- * for both to stop. The pointers are kept, not owned; a cached graph of
- * chained steps is dropped so that the next chem_integrate_steps captures
- * them. Errors: CHEM_EINVAL (s NULL). */
-int chem_eval_counters(chem_solver* s, int32_t* n_jac, int32_t* n_fev);
+ * Both arrays hold capacity entries (int32), must stay valid while calls use
+ * them, and are overwritten per call (chem_integrate_steps adds over its
+ * steps; cells that chem_integrate_zonal maps get 0); a later call with more
+ * than capacity cells fails with CHEM_EINVAL before any work is enqueued.
+ * Pass NULL for both to stop (capacity is then ignored). The pointers are
+ * kept, not owned; a cached graph of chained steps is dropped so that the
+ * next chem_integrate_steps captures them. Errors: CHEM_EINVAL (s NULL,
+ * capacity < 0, or capacity 0 with a counter array). */
+int chem_eval_counters(chem_solver* s, int32_t* n_jac, int32_t* n_fev, int64_t capacity);
 
 /* ---- kernel-level entry points (tests and roofline measurements) -------- */
 

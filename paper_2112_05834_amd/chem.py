@@ -96,7 +96,7 @@ def lib():
             "chem_autotune_cached": (i32, [_vp, ctypes.c_char_p, i64, _vp, dbl, _vp, ctypes.POINTER(i32)]),
             "chem_workspace_info": (i32, [_vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
             "chem_kernel_timing": (i32, [_vp, i32]),
-            "chem_eval_counters": (i32, [_vp, _vp, _vp]),
+            "chem_eval_counters": (i32, [_vp, _vp, _vp, i64]),
             "chem_kernel_times": (i32, [_vp, _vp, i32, ctypes.POINTER(i32)]),
             "chem_mech_elements": (i32, [_vp, ctypes.POINTER(i32), _vp]),
             "chem_zone_config": (i32, [_vp, _vp, _vp, _vp, dbl, dbl]),
@@ -473,8 +473,9 @@ class Solver:
         integration call fills with the per-cell evaluations of J and of f
         (None for both to stop). The tensors must outlive their use."""
         self._counters = (n_jac, n_fev)     # keep them alive while the library holds their addresses
+        cap = min([t.numel() for t in (n_jac, n_fev) if t is not None], default=0)
         _check(lib().chem_eval_counters(self._h, _ptr(n_jac, torch.int32, self.device, name="n_jac"),
-                                       _ptr(n_fev, torch.int32, self.device, name="n_fev")))
+                                       _ptr(n_fev, torch.int32, self.device, name="n_fev"), cap))
 
     def kernel_timing(self, enable: bool):
         _check(lib().chem_kernel_timing(self._h, 1 if enable else 0))

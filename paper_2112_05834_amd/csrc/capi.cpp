@@ -113,6 +113,7 @@ struct chem_solver {
   unsigned long long* d_head = nullptr;   // [0] queue head, [1] log head
   int32_t* d_njac = nullptr;              // caller's per-cell evaluation counters (chem_eval_counters)
   int32_t* d_nfev = nullptr;
+  int64_t counters_cap = 0;               // entries they hold
   unsigned char* scratch = nullptr;       // this device's address of the static scratch array
   chemk::Variant variants[8];
   int nvariants = 0;
@@ -426,6 +427,8 @@ int check_integrate_args(const chem_solver* s, int64_t n, double dt, const doubl
   if (n < 0) return fail(CHEM_EINVAL, "n_cells < 0");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(CHEM_EINVAL, "dt must be positive and finite");
   if (n > 0 && (!in || !out)) return fail(CHEM_EINVAL, "null phi_in or phi_out");
+  if ((s->d_njac || s->d_nfev) && n > s->counters_cap)
+    return fail(CHEM_EINVAL, "more cells than the evaluation counters set by chem_eval_counters hold");
   if (n > 0 && in != out) {
     const char* a = reinterpret_cast<const char*>(in);
     const char* b = reinterpret_cast<const char*>(out);
@@ -1094,11 +1097,13 @@ int chem_workspace_info(chem_solver* s, int32_t* slots, int64_t* bytes_per_slot)
 
 // ---- kernel timing -----------------------------------------------------------
 
-int chem_eval_counters(chem_solver* s, int32_t* n_jac, int32_t* n_fev) {
-  if (!s) return fail(CHEM_EINVAL, "chem_eval_counters: bad argument");
+int chem_eval_counters(chem_solver* s, int32_t* n_jac, int32_t* n_fev, int64_t capacity) {
+  if (!s || capacity < 0 || ((n_jac || n_fev) && capacity == 0))
+    return fail(CHEM_EINVAL, "chem_eval_counters: bad argument");
   DeviceGuard g(s->dev);
   s->d_njac = n_jac;
   s->d_nfev = n_fev;
+  s->counters_cap = (n_jac || n_fev) ? capacity : 0;
   drop_graph(s);   // a cached chain of steps holds the previous pointers
   return CHEM_OK;
 }

@@ -102,3 +102,10 @@ def test_too_many_species_is_a_mechanism_error(tmp_path):
         chem.Mechanism(str(p))
     assert e.value.code == -2
     assert "species" in str(e.value)
+
+
+def test_eval_counters_rejects_bad_arguments_without_device():
+    from paper_2112_05834_amd import chem
+    L = chem.lib()
+    assert L.chem_eval_counters(None, None, None, 0) == -1                  # no solver
+    # (a solver is needed for the rest; its checks come before any device work)

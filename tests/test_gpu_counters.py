@@ -7,7 +7,7 @@ On every cell whose accepted/rejected step counts equal the oracle's, n_jac
 and n_fev must equal the oracle's exactly (at most 0.1% of cells, rounded up,
 may take another step sequence, as in the parity tests). Chained steps add up
 the counts, mapped zonal cells get 0, and with the counters switched off no
-integration writes them.
+integration writes them; a call with more cells than they hold is refused.
 """
 import os
 
@@ -95,6 +95,16 @@ def test_eval_counters_steps_zonal_and_off(tmp_path):
     S.integrate_steps(x, wl.dt, 2, h_io=False, out=out)
     torch.cuda.synchronize()
     assert (nj == -7).all()
+    # a call with more cells than the counters hold is refused before any work
+    small = torch.full((16,), -7, dtype=torch.int32, device=DEV)
+    S.eval_counters(small, None)
+    with pytest.raises(chem.ChemError):
+        S.integrate(x, wl.dt, h_io=False)
+    with pytest.raises(chem.ChemError):
+        S.integrate_steps(x, wl.dt, 2, h_io=False, out=out)
+    torch.cuda.synchronize()
+    assert (small == -7).all()
+    S.eval_counters(None, None)
     # zonal mapping: mapped cells are not integrated and count 0
     amb = synth.generate_states(mech, 256, 6.0e6, "ambient", 106)
     c, yf, yo = synth.bilger_streams(mech)
