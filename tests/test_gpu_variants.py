@@ -70,8 +70,6 @@ def test_variant_matches_oracle(tmp_path, name, n_gpu, n_check, variant):
     """ros4: Shampine's scheme; fd: forward-difference Jacobian; nobath: the
     last species (the bath gas) not integrated, its mass fraction 1 - the
     sum of the others (n = Ns); and the three together."""
-    if variant == "ros4_fd_nobath" and name != "tiny9_1024":
-        pytest.skip("the combination runs on the 9-species cells only")
     wl, mech, path, phi = synth.workload_inputs(name, str(tmp_path), n_cells=n_gpu)
     kw, okw = VARIANTS[variant]
     if "fd" in variant and name == "spray54_262144":
