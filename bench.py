@@ -312,6 +312,9 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-6, help="relative tolerance (default: the Spray A setting)")
     ap.add_argument("--atol", type=float, default=1e-10, help="absolute tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--order", default="generated", choices=("generated", "t-ascending", "t-descending"),
+                    help="cell order: as generated, or sorted by temperature (a mesh-like order that puts the "
+                         "stiff hot cells together)")
     ap.add_argument("--schedules", default="plain,persistent,binned,truebins",
                     help="comma list of plain, persistent, binned, truebins, zonal")
     ap.add_argument("--zone", default="1e-6,1.0", metavar="Z_MAX,T_TOL[,DZ]",
@@ -344,6 +347,9 @@ def main():
 
     d = tempfile.mkdtemp(prefix="chem_bench_")
     wl, mech, path, phi = synth.workload_inputs(args.workload, d, args.cells if args.cells > 0 else None)
+    if args.order != "generated":
+        phi = np.ascontiguousarray(phi[np.argsort(phi[:, 0] if args.order == "t-ascending" else -phi[:, 0],
+                                                  kind="stable")])
     M = chem.Mechanism(path)
     S = chem.Solver(M, chem.default_opts(**TOL), device=0)
     x = torch.from_numpy(phi).to("cuda:0")
@@ -461,7 +467,7 @@ def main():
         achieved = flops / kern_s
     traffic = measured_traffic()
     executed = measured_fp64_ops()
-    if (args.workload != "spray54_262144" or args.chain > 1 or args.cells > 0 or
+    if (args.workload != "spray54_262144" or args.chain > 1 or args.cells > 0 or args.order != "generated" or
             (args.rtol, args.atol) != (1e-6, 1e-10)):
         traffic = None
         executed = None
@@ -481,7 +487,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "cells": n_cells, "species": mech.n_species,
                    "reactions": mech.n_reactions, "pressure_Pa": wl.pressure, "dt_s": wl.dt,
-                   "schedule": head, "chained_steps_per_graph": args.chain, "rtol": args.rtol, "atol": args.atol},
+                   "schedule": head, "chained_steps_per_graph": args.chain, "rtol": args.rtol, "atol": args.atol,
+                   "cell_order": args.order},
         "roofline": {"bound": "alu", "achieved": None if achieved is None else achieved / 1e12,
                      "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": None if achieved is None else achieved / FP64_VECTOR_PEAK,
