@@ -8,6 +8,8 @@
 #define _GNU_SOURCE
 #include "chem_oracle.h"
 
+#include <errno.h>
+#include <limits.h>
 #include <math.h>
 #include <pthread.h>
 #include <stdatomic.h>
@@ -61,8 +63,9 @@ static int tk_next(toks* t, const char** s) {
 static int tk_int(toks* t, int* v) {
   const char* s; char* e;
   if (tk_next(t, &s)) return -1;
+  errno = 0;
   long x = strtol(s, &e, 10);
-  if (*e) return -1;
+  if (*e || errno == ERANGE || x < INT_MIN || x > INT_MAX) return -1;
   *v = (int)x;
   return 0;
 }
@@ -70,7 +73,7 @@ static int tk_dbl(toks* t, double* v) {
   const char* s; char* e;
   if (tk_next(t, &s)) return -1;
   *v = strtod(s, &e);
-  if (*e) return -1;
+  if (*e || !isfinite(*v)) return -1;
   return 0;
 }
 static int tk_expect(toks* t, const char* w) {
@@ -115,18 +118,19 @@ int orc_mech_load(const char* path, orc_mech** out) {
   orc_mech* m = (orc_mech*)calloc(1, sizeof(orc_mech));
   int ne, ver;
   if (tk_expect(&t, "chemmech") || tk_int(&t, &ver) || ver != 1) PFAIL("header");
-  if (tk_expect(&t, "elements") || tk_int(&t, &ne) || ne < 1) PFAIL("elements");
+  /* the size limits keep every array size below int range */
+  if (tk_expect(&t, "elements") || tk_int(&t, &ne) || ne < 1 || ne > 1024) PFAIL("elements");
   for (int e = 0; e < ne; ++e) {
     const char* s; double w;
     if (tk_next(&t, &s) || tk_dbl(&t, &w)) PFAIL("element line");
   }
-  if (tk_expect(&t, "species") || tk_int(&t, &m->ns) || m->ns < 1) PFAIL("species");
+  if (tk_expect(&t, "species") || tk_int(&t, &m->ns) || m->ns < 1 || m->ns > (1 << 16)) PFAIL("species");
   m->ne = ne;
   m->elem = (int*)calloc((size_t)m->ns * ne, sizeof(int));
-  m->W = (double*)calloc(m->ns, sizeof(double));
-  m->trange = (double*)calloc(3 * m->ns, sizeof(double));
-  m->lo = (double*)calloc(7 * m->ns, sizeof(double));
-  m->hi = (double*)calloc(7 * m->ns, sizeof(double));
+  m->W = (double*)calloc((size_t)m->ns, sizeof(double));
+  m->trange = (double*)calloc((size_t)3 * m->ns, sizeof(double));
+  m->lo = (double*)calloc((size_t)7 * m->ns, sizeof(double));
+  m->hi = (double*)calloc((size_t)7 * m->ns, sizeof(double));
   for (int i = 0; i < m->ns; ++i) {
     const char* s; int c;
     if (tk_next(&t, &s) || tk_dbl(&t, &m->W[i])) PFAIL("species line");
@@ -139,7 +143,7 @@ int orc_mech_load(const char* path, orc_mech** out) {
     for (int k = 0; k < 7; ++k) if (tk_dbl(&t, &m->hi[7 * i + k])) PFAIL("nasa hi");
     if (!(m->W[i] > 0)) PFAIL("W <= 0");
   }
-  if (tk_expect(&t, "reactions") || tk_int(&t, &m->nr) || m->nr < 0) PFAIL("reactions");
+  if (tk_expect(&t, "reactions") || tk_int(&t, &m->nr) || m->nr < 0 || m->nr > (1 << 24)) PFAIL("reactions");
   m->rx = (orc_rxn*)calloc(m->nr > 0 ? m->nr : 1, sizeof(orc_rxn));
   for (int r = 0; r < m->nr; ++r) {
     orc_rxn* x = &m->rx[r];

@@ -3,6 +3,8 @@
 #include "mech.hpp"
 
 #include <algorithm>
+#include <cerrno>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -26,8 +28,9 @@ struct Tok {
     std::string s;
     if (!next(s)) return false;
     char* e = nullptr;
+    errno = 0;
     long x = std::strtol(s.c_str(), &e, 10);
-    if (*e) return false;
+    if (*e || errno == ERANGE || x < INT_MIN || x > INT_MAX) return false;
     v = static_cast<int>(x);
     return true;
   }
@@ -52,7 +55,8 @@ bool side(Tok& tk, int ns, std::vector<std::pair<int, int>>& out) {
   std::vector<int> order;
   for (int j = 0; j < k; ++j) {
     int s, o;
-    if (!tk.integer(s) || !tk.integer(o) || s < 0 || s >= ns || o < 1) return false;
+    // an order above 3 is rejected here, so that merged orders stay small
+    if (!tk.integer(s) || !tk.integer(o) || s < 0 || s >= ns || o < 1 || o > 3) return false;
     if (!acc.count(s)) order.push_back(s);
     acc[s] += o;
   }
